@@ -1,0 +1,215 @@
+/*
+ * md.h -- C ABI of the MI355X EAM timestep library (libmdeam.so).
+ *
+ * The library advances Embedded Atom Method molecular dynamics on one GPU:
+ * cell binning, a Verlet neighbour list with skin, the density pass
+ * rho_i = sum_j rho(r_ij), the embedding derivative F'(rho_i), the force pass
+ * and leap-frog / velocity-Verlet integration.  Paper: "Breaking the Molecular
+ * Dynamics Timescale Barrier Using a Wafer-Scale System" (arXiv 2405.07898):
+ *   - per-atom state is identity, position and velocity          (Sec. III-A)
+ *   - rho, F and phi are polynomial splines with a hard cutoff    (Sec. II-A)
+ *   - U = 1/2 sum_{i!=j} phi(r_ij) + sum_i F(rho_i)               (Eq. potential)
+ *   - force = -dU/dx_i                                             (Eq. EAMforce)
+ *   - second-order leap-frog time stepping                         (Eq. leapfrog)
+ *   - only the MD loop is timed; setup sits outside md_step        (Sec. IV-B)
+ *
+ * Conventions
+ *   - Units: Angstrom, fs, eV, amu.  ftm2v converts (eV/A)/amu to A/fs^2.
+ *   - Every state array crossing the boundary is a DEVICE pointer to float64
+ *     AoS [n_atoms][3] in the caller's original atom order (replicas
+ *     concatenated in replica order).  Spline tables and per-replica sizes
+ *     are HOST pointers, copied during md_create.
+ *   - The caller owns all device memory.  md_create borrows a workspace of
+ *     md_workspace_size() bytes (256-byte aligned) until md_destroy; the
+ *     library allocates no device memory of its own apart from what the HIP
+ *     runtime needs to instantiate graphs.
+ *   - A context is bound to one HIP stream (hipStream_t passed as void*);
+ *     every call enqueues on it.  Calls that return host values (md_energy,
+ *     md_stats, md_step's status) synchronise that stream.  A context is not
+ *     thread-safe.
+ *   - Device-side conditions are latched in a status word read at the end of
+ *     md_step / md_build_neighbors.  After an error every kernel of the
+ *     context becomes a no-op until md_set_state or md_restore_checkpoint.
+ */
+#ifndef MDEAM_MD_H
+#define MDEAM_MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t md_status;
+
+/* Status codes: 0 ok, < 0 error, > 0 warning (sticky bits). */
+#define MD_OK 0
+#define MD_E_ARG (-1)           /* invalid argument */
+#define MD_E_BOX (-2)           /* box edge < 2 (r_cut + skin) or < 3 cells per edge */
+#define MD_E_TABLE (-3)         /* malformed spline table */
+#define MD_E_NBR_OVERFLOW (-4)  /* some atom has more than nbr_capacity list entries */
+#define MD_E_CELL_OVERFLOW (-5) /* some cell holds more than cell_capacity atoms */
+#define MD_E_NONFINITE (-6)     /* non-finite position or force */
+#define MD_E_HIP (-7)           /* HIP runtime error (see md_last_error) */
+#define MD_E_ORDER (-8)         /* call out of order (e.g. md_step before md_build_neighbors) */
+#define MD_E_LOST_ATOM (-9)     /* an atom left the periodic box by more than one box length */
+#define MD_E_WORKSPACE (-10)    /* workspace too small or misaligned */
+#define MD_W_RHO_RANGE 1        /* some rho_i exceeded the F table; last cubic extrapolated */
+
+/* Precision of the pair passes. */
+#define MD_FP64 0  /* everything in float64 */
+#define MD_MIXED 1 /* pair terms, rho_i and force sums in float32 with compensated
+                      (TwoSum) accumulation; positions, velocities, integration
+                      and energy totals in float64 */
+
+/* A cubic spline on equally spaced knots x0 + k/inv_dx, k = 0..n_knots-1.
+ * coef (host) holds (n_knots-1) rows of 4 float64: segment k evaluates
+ * c0 + c1 t + c2 t^2 + c3 t^3 with t = (s - x0) inv_dx - k in [0,1); the
+ * segment index is int((s - x0) inv_dx) clamped to [0, n_knots-2], so values
+ * past the last knot extrapolate the last cubic (segment arithmetic as in the
+ * paper's Table "flopmodel": x = alpha r, k = int(x), dx = x - k). */
+typedef struct md_spline {
+  int32_t n_knots;
+  int32_t reserved;
+  double x0;
+  double inv_dx;
+  const double* coef;
+} md_spline;
+
+/* Parameters shared by all replicas of a context. */
+typedef struct md_params {
+  double mass;           /* amu */
+  double dt;             /* fs */
+  double r_cut;          /* interaction cutoff, A (pairs with r^2 < r_cut^2 interact) */
+  double skin;           /* Verlet skin, A (list holds pairs with r^2 < (r_cut+skin)^2) */
+  double ftm2v;          /* (eV/A)/amu -> A/fs^2 */
+  double kboltz;         /* eV/K, for temperatures reported by md_stats */
+  int32_t precision;     /* MD_FP64 or MD_MIXED */
+  int32_t nbr_capacity;  /* max list entries per atom (<= 1024) */
+  int32_t cell_capacity; /* max atoms per binning cell (<= 256) */
+  int32_t chunk_steps;   /* steps per captured hipGraph (even, >= 2), e.g. 100 */
+  int32_t lanes_per_atom;/* 0 = automatic, else 1, 2, 4 or 8 lanes per atom */
+  int32_t sort_every;    /* re-sort atoms by cell every this many chunks (0 = never) */
+} md_params;
+
+typedef struct md_ctx md_ctx;
+
+/* Counters and observables; md_stats fills it (synchronises). */
+typedef struct md_stats_t {
+  int64_t steps;        /* MD steps taken since md_build_neighbors */
+  int64_t rebuilds;     /* neighbour-list rebuilds inside md_step */
+  int64_t list_entries; /* total list entries at the last build (mean length = /n_atoms) */
+  int32_t max_list;     /* longest list at the last build */
+  int32_t max_cell;     /* fullest cell at the last binning */
+  int32_t status_bits;  /* latched device status bits */
+  int32_t reserved;
+} md_stats_t;
+
+/* Bytes of device workspace md_create needs for these sizes.
+ * n_rep replicas; rep_atoms[r] atoms and cubic-or-orthorhombic periodic box
+ * rep_box[3r..3r+2] (A) for replica r (host arrays). */
+md_status md_workspace_size(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                            const double* rep_box, size_t* bytes);
+
+/* Create a context.  phi(r), rho(r) tables must cover [0, r_cut]; emb(rho)
+ * any range (values past its last knot raise MD_W_RHO_RANGE).  workspace is
+ * a device pointer of at least md_workspace_size() bytes; stream is a
+ * hipStream_t.  Returns MD_E_BOX if any replica edge is below
+ * 2 (r_cut + skin) or gives fewer than 3 cells. */
+md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                    const double* rep_box, const md_spline* phi, const md_spline* rho,
+                    const md_spline* emb, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Upload positions x and on-step velocities v (device, [n][3] float64,
+ * original order).  Positions are wrapped into the box.  Clears the status
+ * word; md_build_neighbors must follow before md_step. */
+md_status md_set_state(md_ctx* ctx, const double* x, const double* v);
+
+/* Sort atoms by cell, bin them, build the Verlet list (pairs with
+ * r^2 < (r_cut+skin)^2 under the minimum image), and compute rho, F' and
+ * forces at the current positions (paper Sec. III-A steps 1-3). */
+md_status md_build_neighbors(md_ctx* ctx);
+
+/* Advance n steps.  Each step: density pass, force pass fused with the
+ * leap-frog kick and drift and the skin/2 displacement check; the list is
+ * rebuilt on the device in the step after any atom moved more than skin/2.
+ * Whole chunks run as one captured hipGraph.  On an error the state rolls
+ * back to the start of the chunk in which it occurred (the status is
+ * returned; md_stats().steps tells where). */
+md_status md_step(md_ctx* ctx, int64_t n);
+
+/* Potential and kinetic energy per replica (host arrays of n_rep doubles;
+ * either may be NULL), with on-step velocities.  Fixed-order reductions:
+ * bitwise reproducible. */
+md_status md_energy(md_ctx* ctx, double* pe, double* ke);
+
+/* Download state in original order (device pointers, [n][3] float64; any
+ * may be NULL): wrapped positions, on-step velocities, forces. */
+md_status md_get_state(md_ctx* ctx, double* x, double* v, double* f);
+
+/* Recompute forces at the current positions (fresh list); same outputs as
+ * md_get_state's f, also giving rho_i and F'_i (device [n] float64, NULL
+ * allowed).  Used for force-error reports. */
+md_status md_compute_forces(md_ctx* ctx, double* f, double* rho, double* fp);
+
+/* Counters (synchronises). */
+md_status md_stats(md_ctx* ctx, md_stats_t* out);
+
+/* Inspection of the last build, original order and original ids (device
+ * pointers): cell id of each atom within its replica, list length and up
+ * to cap_out list entries per atom (row-major [n][cap_out], unused -1). */
+md_status md_get_cells(md_ctx* ctx, int32_t* cell);
+md_status md_get_neighbors(md_ctx* ctx, int32_t* cnt, int32_t* nbr, int32_t cap_out);
+
+/* Enqueue reps launches of one pass on the context stream, with no
+ * synchronisation, for timing with events: 0 = density, 1 = force+integrate
+ * (advances the state), 2 = list build, 3 = binning. */
+md_status md_launch_pass(md_ctx* ctx, int32_t pass, int32_t reps);
+
+/* Last error text of this context (or of the library when ctx is NULL). */
+const char* md_last_error(const md_ctx* ctx);
+const char* md_status_string(md_status s);
+
+void md_destroy(md_ctx* ctx);
+
+/* ------------------------------------------------------------------ */
+/* Force matching (gradient of a force-matching loss w.r.t. the spline
+ * coefficients).  Configurations are static periodic boxes; the loss is
+ * L = sum_c sum_i |F_i - Fref_i|^2 with forces from Eq. (EAMforce).
+ * The gradient is taken with respect to the per-segment coefficients of
+ * phi, rho and F (layouts as md_spline.coef). */
+typedef struct md_fm_ctx md_fm_ctx;
+
+/* Bytes of device workspace for n_cfg configs (host rep_atoms, rep_box) with
+ * n_knots-knot tables for each of phi, rho, F. */
+md_status md_fm_workspace_size(int32_t n_cfg, const int64_t* cfg_atoms, const double* cfg_box,
+                               double r_cut, int32_t nbr_capacity, const int32_t n_knots[3],
+                               size_t* bytes);
+
+/* x and fref: device [n][3] float64 (all configs concatenated).  The knot
+ * grids (x0, inv_dx, n_knots) of the three tables are fixed here; their
+ * coefficients are passed to each forward call. */
+md_status md_fm_create(md_fm_ctx** out, int32_t n_cfg, const int64_t* cfg_atoms,
+                       const double* cfg_box, double r_cut, int32_t nbr_capacity,
+                       const md_spline* grid_phi, const md_spline* grid_rho,
+                       const md_spline* grid_emb, const double* x, const double* fref,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Forward: coefficients (device, [(n_knots-1)*4] float64 each) -> loss (host
+ * double) and, if f_out is not NULL, forces (device [n][3]). */
+md_status md_fm_forward(md_fm_ctx* ctx, const double* coef_phi, const double* coef_rho,
+                        const double* coef_emb, double* loss, double* f_out);
+
+/* Backward for the last forward: dL/dcoef into device arrays of the same
+ * layouts (overwritten), scaled by seed (dL_total/dL). Deterministic. */
+md_status md_fm_backward(md_fm_ctx* ctx, double seed, double* g_phi, double* g_rho,
+                         double* g_emb);
+
+void md_fm_destroy(md_fm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDEAM_MD_H */

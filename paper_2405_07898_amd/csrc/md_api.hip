@@ -1,0 +1,760 @@
+// md_api.hip -- host side of the EAM library: contexts, workspace carving,
+// tile tables, spline-table layouts, step graphs and the C ABI of md.h.
+#include "md.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+
+using namespace mdk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Carve {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct RepHost {
+  int64_t n;
+  double box[3];
+  int32_t nc[3];
+};
+
+bool valid_spline(const md_spline* s) {
+  return s && s->coef && s->n_knots >= 3 && std::isfinite(s->x0) && std::isfinite(s->inv_dx) &&
+         s->inv_dx > 0.0;
+}
+
+md_status check_params(const md_params* p) {
+  if (!p) return MD_E_ARG;
+  if (!(p->mass > 0) || !(p->dt >= 0) || !(p->r_cut > 0) || !(p->skin >= 0) || !(p->ftm2v > 0))
+    return MD_E_ARG;
+  if (p->precision != MD_FP64 && p->precision != MD_MIXED) return MD_E_ARG;
+  if (p->nbr_capacity < 1 || p->nbr_capacity > kMaxNbrCap) return MD_E_ARG;
+  if (p->cell_capacity < 1 || p->cell_capacity > kMaxCellCap) return MD_E_ARG;
+  if (p->chunk_steps < 2 || (p->chunk_steps & 1)) return MD_E_ARG;
+  const int l = p->lanes_per_atom;
+  if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8)) return MD_E_ARG;
+  if (p->sort_every < 0) return MD_E_ARG;
+  return MD_OK;
+}
+
+// Cells per edge: floor(L / (r_cut + skin)), at least 3; L >= 2 (r_cut + skin)
+// keeps the minimum image unique inside the list radius.
+md_status rep_cells(const md_params* p, const double* box, int32_t nc[3]) {
+  const double rl = p->r_cut + p->skin;
+  for (int d = 0; d < 3; ++d) {
+    if (!(box[d] >= 2.0 * rl) || !std::isfinite(box[d])) return MD_E_BOX;
+    const double q = std::floor(box[d] / rl);
+    if (q < 3.0 || q > 4096.0) return MD_E_BOX;
+    nc[d] = (int32_t)q;
+  }
+  return MD_OK;
+}
+
+// XCD-aware order: block b runs on XCD b % 8; give each XCD a contiguous run
+// of tiles so neighbouring tiles share that XCD's L2.
+template <class T>
+std::vector<T> xcd_order(const std::vector<T>& tiles, const T& idle) {
+  const size_t n = tiles.size();
+  const size_t per = (n + kXcd - 1) / kXcd;
+  std::vector<T> out(per * kXcd, idle);
+  for (size_t b = 0; b < out.size(); ++b) {
+    const size_t t = (b % kXcd) * per + b / kXcd;
+    if (t < n) out[b] = tiles[t];
+  }
+  return out;
+}
+
+struct LayoutSizes {
+  int64_t n = 0;
+  int64_t cells = 0;
+  size_t atile_blocks = 0, ctile_blocks = 0;
+};
+
+}  // namespace
+
+struct md_ctx {
+  md_params p{};
+  int32_t n_rep = 0;
+  std::vector<RepHost> reps;
+  LayoutSizes sz;
+  Geometry g{};
+  State st[2]{};  // st[c].pos = current buffer when cur == c
+  Tables t{};
+  Launch L{};
+  double4* pos_buf[2]{};
+  double4* snap_pos = nullptr;
+  double4* snap_vel = nullptr;
+  double* energy_dev = nullptr;
+  int32_t* status = nullptr;
+  int cur = 0;
+  int lpa = 1;
+  bool has_state = false;
+  bool built = false;
+  bool v_half = false;  // velocities are half-step (after build)
+  int64_t chunks_since_sort = 0;
+  hipGraphExec_t graph = nullptr;
+  std::string err;
+};
+
+struct md_fm_ctx;
+
+namespace {
+
+md_status hip_fail(md_ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (c) c->err = m;
+  g_last_error = m;
+  return MD_E_HIP;
+}
+
+#define HIPC(ctx, expr)                                  \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+LayoutSizes layout(const md_params* p, int32_t n_rep, const std::vector<RepHost>& reps) {
+  LayoutSizes s;
+  size_t at = 0, ct = 0;
+  for (int r = 0; r < n_rep; ++r) {
+    s.n += reps[r].n;
+    const int64_t nc = (int64_t)reps[r].nc[0] * reps[r].nc[1] * reps[r].nc[2];
+    s.cells += nc;
+    at += (size_t)((reps[r].n + 63) / 64);
+    ct += (size_t)nc;
+  }
+  s.atile_blocks = ((at + kXcd - 1) / kXcd) * kXcd;
+  s.ctile_blocks = ((ct + kXcd - 1) / kXcd) * kXcd;
+  (void)p;
+  return s;
+}
+
+struct Buffers {
+  RepDev* reps;
+  AtomTile* atiles;
+  CellTile* ctiles;
+  double4 *rho_val, *phi_val, *dpair_a, *emb_val;
+  double2* dpair_b;
+  float4 *rho_val32, *dpair_a32;
+  float2* dpair_b32;
+  double4 *pos0, *pos1, *vel, *xref, *frc;
+  double *rho, *epair;
+  int32_t *id, *cell_of, *cnt;
+  uint32_t* nbr;
+  int32_t *bin_cnt, *bin_idx, *cell_start, *status;
+  double4 *sort_pos, *sort_vel;
+  int32_t* sort_id;
+  double4 *snap_pos, *snap_vel;
+  double *partial, *energy;
+};
+
+size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s, int nr, int ne,
+             Buffers* b) {
+  Carve c;
+  c.base = base;
+  const size_t N = (size_t)std::max<int64_t>(s.n, 1);
+  Buffers tmp;
+  Buffers& o = b ? *b : tmp;
+  o.reps = c.take<RepDev>(n_rep);
+  o.atiles = c.take<AtomTile>(s.atile_blocks);
+  o.ctiles = c.take<CellTile>(s.ctile_blocks);
+  o.rho_val = c.take<double4>(nr - 1);
+  o.phi_val = c.take<double4>(nr - 1);
+  o.dpair_a = c.take<double4>(nr - 1);
+  o.dpair_b = c.take<double2>(nr - 1);
+  o.emb_val = c.take<double4>(ne - 1);
+  o.rho_val32 = c.take<float4>(nr - 1);
+  o.dpair_a32 = c.take<float4>(nr - 1);
+  o.dpair_b32 = c.take<float2>(nr - 1);
+  o.pos0 = c.take<double4>(N);
+  o.pos1 = c.take<double4>(N);
+  o.vel = c.take<double4>(N);
+  o.xref = c.take<double4>(N);
+  o.frc = c.take<double4>(N);
+  o.rho = c.take<double>(N);
+  o.epair = c.take<double>(N);
+  o.id = c.take<int32_t>(N);
+  o.cell_of = c.take<int32_t>(N);
+  o.cnt = c.take<int32_t>(N);
+  o.nbr = c.take<uint32_t>(N * (size_t)p->nbr_capacity);
+  o.bin_cnt = c.take<int32_t>((size_t)s.cells);
+  o.bin_idx = c.take<int32_t>((size_t)s.cells * p->cell_capacity);
+  o.cell_start = c.take<int32_t>((size_t)s.cells + 1);
+  o.status = c.take<int32_t>(SW_WORDS);
+  o.sort_pos = c.take<double4>(N);
+  o.sort_vel = c.take<double4>(N);
+  o.sort_id = c.take<int32_t>(N);
+  o.snap_pos = c.take<double4>(N);
+  o.snap_vel = c.take<double4>(N);
+  o.partial = c.take<double>(2 * s.atile_blocks);
+  o.energy = c.take<double>(2 * (size_t)n_rep);
+  return (c.off + 255) & ~size_t(255);
+}
+
+md_status gather_reps(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                      const double* rep_box, std::vector<RepHost>* out) {
+  if (n_rep < 1 || !rep_atoms || !rep_box) return MD_E_ARG;
+  out->resize(n_rep);
+  int64_t tot = 0;
+  for (int r = 0; r < n_rep; ++r) {
+    RepHost& h = (*out)[r];
+    h.n = rep_atoms[r];
+    if (h.n < 1) return MD_E_ARG;
+    tot += h.n;
+    for (int d = 0; d < 3; ++d) h.box[d] = rep_box[3 * r + d];
+    md_status s = rep_cells(p, h.box, h.nc);
+    if (s != MD_OK) return s;
+  }
+  if (tot >= (int64_t(1) << kIndexBits)) return MD_E_ARG;
+  return MD_OK;
+}
+
+int auto_lpa(int64_t n) {
+  if (n <= 32768) return 8;
+  if (n <= 262144) return 4;
+  return 2;
+}
+
+md_status read_status(md_ctx* c, int32_t* words) {
+  HIPC(c, hipMemcpyAsync(words, c->status, SW_WORDS * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         c->L.stream));
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  return MD_OK;
+}
+
+md_status status_code(int32_t bits) {
+  if (bits & ST_NBR_OVERFLOW) return MD_E_NBR_OVERFLOW;
+  if (bits & ST_CELL_OVERFLOW) return MD_E_CELL_OVERFLOW;
+  if (bits & ST_LOST) return MD_E_LOST_ATOM;
+  if (bits & ST_NONFINITE) return MD_E_NONFINITE;
+  if (bits & ST_RHO_RANGE) return MD_W_RHO_RANGE;
+  return MD_OK;
+}
+
+// Sort by cell (new slot order), then bin and build the list, leaving the
+// bins zeroed.  Positions are wrapped; x_ref is reset.
+md_status rebuild_sorted(md_ctx* c, bool sort) {
+  State& s = c->st[c->cur];
+  HIPC(c, hipMemsetAsync(c->status + SW_FLAG0, 0, 2 * sizeof(int32_t), c->L.stream));
+  if (sort) HIPC(c, launch_sort(c->L, c->g, s, c->sz.cells));
+  HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+  HIPC(c, launch_bin(c->L, c->g, s, nullptr));
+  HIPC(c, launch_build(c->L, c->g, s, nullptr));
+  HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+  return MD_OK;
+}
+
+md_status forces_now(md_ctx* c, bool want_rho) {
+  State& s = c->st[c->cur];
+  HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, nullptr, nullptr,
+                         c->sz.cells, want_rho));
+  HIPC(c, launch_force_only(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos));
+  return MD_OK;
+}
+
+// One step with eager launches (parity cur -> 1 - cur).
+md_status step_eager(md_ctx* c) {
+  const int k = c->cur;
+  State& s = c->st[k];
+  int32_t* fl_cur = c->status + (k == 0 ? SW_FLAG0 : SW_FLAG1);
+  int32_t* fl_nxt = c->status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
+  HIPC(c, launch_bin(c->L, c->g, s, fl_cur));
+  HIPC(c, launch_build(c->L, c->g, s, fl_cur));
+  HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, fl_cur, fl_nxt,
+                         c->sz.cells, false));
+  HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
+                                 c->st[1 - k].pos, fl_nxt));
+  c->cur = 1 - k;
+  return MD_OK;
+}
+
+md_status capture_chunk(md_ctx* c) {
+  if (c->graph) return MD_OK;
+  hipGraph_t gr = nullptr;
+  HIPC(c, hipStreamBeginCapture(c->L.stream, hipStreamCaptureModeRelaxed));
+  const int saved = c->cur;
+  md_status rc = MD_OK;
+  for (int k = 0; k < c->p.chunk_steps && rc == MD_OK; ++k) rc = step_eager(c);
+  c->cur = saved;
+  hipError_t e = hipStreamEndCapture(c->L.stream, &gr);
+  if (rc != MD_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    c->graph = nullptr;
+    return hip_fail(c, e, "hipGraphInstantiate");
+  }
+  return MD_OK;
+}
+
+// Library tables from the caller's per-segment coefficients.
+void build_tables(const md_spline* phi, const md_spline* rho, const md_spline* emb,
+                  std::vector<double4>* rv, std::vector<double4>* pv, std::vector<double4>* da,
+                  std::vector<double2>* db, std::vector<double4>* ev, std::vector<float4>* rv32,
+                  std::vector<float4>* da32, std::vector<float2>* db32) {
+  const int ns = rho->n_knots - 1;
+  const double a = rho->inv_dx;
+  rv->resize(ns);
+  pv->resize(ns);
+  da->resize(ns);
+  db->resize(ns);
+  rv32->resize(ns);
+  da32->resize(ns);
+  db32->resize(ns);
+  for (int k = 0; k < ns; ++k) {
+    const double* r = rho->coef + 4 * k;
+    const double* f = phi->coef + 4 * k;
+    (*rv)[k] = make_double4(r[0], r[1], r[2], r[3]);
+    (*pv)[k] = make_double4(f[0], f[1], f[2], f[3]);
+    // derivative cubics in t, pre-scaled by alpha: f'(t) = (c1 + 2 c2 t + 3 c3 t^2) alpha
+    (*da)[k] = make_double4(r[1] * a, 2.0 * r[2] * a, 3.0 * r[3] * a, f[1] * a);
+    (*db)[k] = make_double2(2.0 * f[2] * a, 3.0 * f[3] * a);
+    (*rv32)[k] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
+    const double4 q = (*da)[k];
+    (*da32)[k] = make_float4((float)q.x, (float)q.y, (float)q.z, (float)q.w);
+    (*db32)[k] = make_float2((float)(*db)[k].x, (float)(*db)[k].y);
+  }
+  const int ne = emb->n_knots - 1;
+  ev->resize(ne);
+  for (int k = 0; k < ne; ++k) {
+    const double* e = emb->coef + 4 * k;
+    (*ev)[k] = make_double4(e[0], e[1], e[2], e[3]);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* md_status_string(md_status s) {
+  switch (s) {
+    case MD_OK: return "ok";
+    case MD_E_ARG: return "invalid argument";
+    case MD_E_BOX: return "box smaller than 2 (r_cut + skin) or fewer than 3 cells per edge";
+    case MD_E_TABLE: return "malformed spline table";
+    case MD_E_NBR_OVERFLOW: return "neighbour list capacity exceeded";
+    case MD_E_CELL_OVERFLOW: return "cell capacity exceeded";
+    case MD_E_NONFINITE: return "non-finite position or force";
+    case MD_E_HIP: return "HIP runtime error";
+    case MD_E_ORDER: return "call out of order";
+    case MD_E_LOST_ATOM: return "atom moved more than one box length";
+    case MD_E_WORKSPACE: return "workspace too small or misaligned";
+    case MD_W_RHO_RANGE: return "warning: density beyond the embedding table";
+    default: return "unknown status";
+  }
+}
+
+const char* md_last_error(const md_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+md_status md_workspace_size(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                            const double* rep_box, size_t* bytes) {
+  md_status s = check_params(p);
+  if (s != MD_OK) return s;
+  if (!bytes) return MD_E_ARG;
+  std::vector<RepHost> reps;
+  if ((s = gather_reps(p, n_rep, rep_atoms, rep_box, &reps)) != MD_OK) return s;
+  LayoutSizes ls = layout(p, n_rep, reps);
+  // the table sizes are not known here: reserve for up to 8192 knots each
+  *bytes = carve(nullptr, p, n_rep, ls, 8192, 8192, nullptr);
+  return MD_OK;
+}
+
+md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                    const double* rep_box, const md_spline* phi, const md_spline* rho,
+                    const md_spline* emb, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return MD_E_ARG;
+  *out = nullptr;
+  md_status s = check_params(p);
+  if (s != MD_OK) return s;
+  if (!valid_spline(phi) || !valid_spline(rho) || !valid_spline(emb)) return MD_E_TABLE;
+  if (phi->n_knots != rho->n_knots || phi->inv_dx != rho->inv_dx || phi->x0 != 0.0 ||
+      rho->x0 != 0.0 || phi->n_knots > 8192 || emb->n_knots > 8192)
+    return MD_E_TABLE;
+  // the r tables must reach r_cut
+  if ((double)(rho->n_knots - 1) / rho->inv_dx < p->r_cut * (1.0 - 1e-12)) return MD_E_TABLE;
+  std::vector<RepHost> reps;
+  if ((s = gather_reps(p, n_rep, rep_atoms, rep_box, &reps)) != MD_OK) return s;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return MD_E_WORKSPACE;
+  LayoutSizes ls = layout(p, n_rep, reps);
+  const size_t need = carve(nullptr, p, n_rep, ls, 8192, 8192, nullptr);
+  if (workspace_bytes < need) return MD_E_WORKSPACE;
+
+  md_ctx* c = new (std::nothrow) md_ctx();
+  if (!c) return MD_E_ARG;
+  c->p = *p;
+  c->n_rep = n_rep;
+  c->reps = reps;
+  c->sz = ls;
+  c->L.stream = reinterpret_cast<hipStream_t>(stream);
+  c->L.atile_blocks = (int32_t)ls.atile_blocks;
+  c->L.ctile_blocks = (int32_t)ls.ctile_blocks;
+  c->lpa = p->lanes_per_atom ? p->lanes_per_atom : auto_lpa(ls.n / n_rep);
+
+  Buffers b;
+  carve(reinterpret_cast<char*>(workspace), p, n_rep, ls, rho->n_knots, emb->n_knots, &b);
+
+  // replica table, atom tiles (64 atoms, aligned to replicas), cell tiles
+  std::vector<RepDev> rd(n_rep);
+  std::vector<AtomTile> at;
+  std::vector<CellTile> ct;
+  int64_t a0 = 0, c0 = 0;
+  const double rl = p->r_cut + p->skin;
+  (void)rl;
+  for (int r = 0; r < n_rep; ++r) {
+    RepDev& d = rd[r];
+    memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 3; ++k) {
+      d.box[k] = reps[r].box[k];
+      d.half[k] = 0.5 * reps[r].box[k];
+      d.nc[k] = reps[r].nc[k];
+      d.inv_cell[k] = (double)reps[r].nc[k] / reps[r].box[k];
+    }
+    d.atom0 = a0;
+    d.n_atoms = (int32_t)reps[r].n;
+    d.cell0 = (int32_t)c0;
+    d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
+    for (int64_t t0 = 0; t0 < reps[r].n; t0 += 64)
+      at.push_back(AtomTile{r, (int32_t)(a0 + t0), (int32_t)std::min<int64_t>(64, reps[r].n - t0), 0});
+    for (int32_t q = 0; q < d.ncell; ++q) ct.push_back(CellTile{r, q});
+    a0 += reps[r].n;
+    c0 += d.ncell;
+  }
+  std::vector<AtomTile> atx = xcd_order(at, AtomTile{0, 0, 0, 0});
+  std::vector<CellTile> ctx = xcd_order(ct, CellTile{0, -1});
+
+  std::vector<double4> rv, pv, da, ev;
+  std::vector<double2> db;
+  std::vector<float4> rv32, da32;
+  std::vector<float2> db32;
+  build_tables(phi, rho, emb, &rv, &pv, &da, &db, &ev, &rv32, &da32, &db32);
+
+#define UP(dst, vec)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = hipMemcpy(dst, vec.data(), vec.size() * sizeof(vec[0]), hipMemcpyHostToDevice); \
+    if (e_ != hipSuccess) {                                                                   \
+      md_status r_ = hip_fail(c, e_, "upload " #vec);                                         \
+      delete c;                                                                               \
+      return r_;                                                                              \
+    }                                                                                         \
+  } while (0)
+  UP(b.reps, rd);
+  UP(b.atiles, atx);
+  UP(b.ctiles, ctx);
+  UP(b.rho_val, rv);
+  UP(b.phi_val, pv);
+  UP(b.dpair_a, da);
+  UP(b.dpair_b, db);
+  UP(b.emb_val, ev);
+  UP(b.rho_val32, rv32);
+  UP(b.dpair_a32, da32);
+  UP(b.dpair_b32, db32);
+#undef UP
+  hipError_t e = hipMemset(b.status, 0, SW_WORDS * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(b.bin_cnt, 0, (size_t)ls.cells * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(b.cnt, 0, (size_t)ls.n * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(b.frc, 0, (size_t)ls.n * sizeof(double4));
+  if (e != hipSuccess) {
+    md_status r_ = hip_fail(c, e, "hipMemset");
+    delete c;
+    return r_;
+  }
+
+  Geometry& g = c->g;
+  g.reps = b.reps;
+  g.atiles = b.atiles;
+  g.ctiles = b.ctiles;
+  g.n = ls.n;
+  g.n_atiles = (int32_t)ls.atile_blocks;
+  g.n_ctiles = (int32_t)ls.ctile_blocks;
+  g.nbr_cap = p->nbr_capacity;
+  g.cell_cap = p->cell_capacity;
+  g.rc2 = p->r_cut * p->r_cut;
+  g.rl2 = (p->r_cut + p->skin) * (p->r_cut + p->skin);
+  g.lim2 = 0.25 * p->skin * p->skin;
+  g.dt = p->dt;
+  g.acc = p->ftm2v / p->mass;
+  g.rc2f = (float)g.rc2;
+
+  Tables& t = c->t;
+  t.rho_val = b.rho_val;
+  t.phi_val = b.phi_val;
+  t.dpair_a = b.dpair_a;
+  t.dpair_b = b.dpair_b;
+  t.emb_val = b.emb_val;
+  t.rho_val32 = b.rho_val32;
+  t.dpair_a32 = b.dpair_a32;
+  t.dpair_b32 = b.dpair_b32;
+  t.r_inv_dx = rho->inv_dx;
+  t.r_inv_dx32 = (float)rho->inv_dx;
+  t.e_x0 = emb->x0;
+  t.e_inv_dx = emb->inv_dx;
+  t.nr = rho->n_knots;
+  t.ne = emb->n_knots;
+
+  State base{};
+  base.vel = b.vel;
+  base.xref = b.xref;
+  base.frc = b.frc;
+  base.rho = b.rho;
+  base.epair = b.epair;
+  base.id = b.id;
+  base.cell_of = b.cell_of;
+  base.nbr = b.nbr;
+  base.cnt = b.cnt;
+  base.bin_cnt = b.bin_cnt;
+  base.bin_idx = b.bin_idx;
+  base.cell_start = b.cell_start;
+  base.status = b.status;
+  base.sort_pos = b.sort_pos;
+  base.sort_vel = b.sort_vel;
+  base.sort_id = b.sort_id;
+  base.partial = b.partial;
+  c->st[0] = base;
+  c->st[1] = base;
+  c->st[0].pos = b.pos0;
+  c->st[0].pos_alt = b.pos1;
+  c->st[1].pos = b.pos1;
+  c->st[1].pos_alt = b.pos0;
+  c->pos_buf[0] = b.pos0;
+  c->pos_buf[1] = b.pos1;
+  c->snap_pos = b.snap_pos;
+  c->snap_vel = b.snap_vel;
+  c->energy_dev = b.energy;
+  c->status = b.status;
+  *out = c;
+  return MD_OK;
+}
+
+md_status md_set_state(md_ctx* c, const double* x, const double* v) {
+  if (!c || !x || !v) return MD_E_ARG;
+  c->cur = 0;
+  HIPC(c, hipMemsetAsync(c->status, 0, SW_WORDS * sizeof(int32_t), c->L.stream));
+  HIPC(c, launch_import(c->L, c->g, c->st[0], x, v));
+  c->has_state = true;
+  c->built = false;
+  c->v_half = false;
+  int32_t w[SW_WORDS];
+  md_status s = read_status(c, w);
+  if (s != MD_OK) return s;
+  return status_code(w[SW_BITS] & ST_ERR_MASK);
+}
+
+md_status md_build_neighbors(md_ctx* c) {
+  if (!c) return MD_E_ARG;
+  if (!c->has_state) return MD_E_ORDER;
+  md_status s = rebuild_sorted(c, true);
+  if (s != MD_OK) return s;
+  if ((s = forces_now(c, false)) != MD_OK) return s;
+  if (!c->v_half) {
+    HIPC(c, launch_halfkick(c->L, c->g, c->st[c->cur], -0.5 * c->p.dt * c->g.acc));
+    c->v_half = true;
+  }
+  c->chunks_since_sort = 0;
+  HIPC(c, hipMemsetAsync(c->status + SW_STEPS, 0, 2 * sizeof(int32_t), c->L.stream));
+  int32_t w[SW_WORDS];
+  if ((s = read_status(c, w)) != MD_OK) return s;
+  s = status_code(w[SW_BITS]);
+  c->built = (s >= 0);
+  return s;
+}
+
+md_status md_step(md_ctx* c, int64_t n) {
+  if (!c || n < 0) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  md_status s;
+  int64_t done = 0;
+  const int chunk = c->p.chunk_steps;
+  HIPC(c, launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, false));
+  while (done < n) {
+    if (c->cur == 0 && n - done >= chunk) {
+      if (c->p.sort_every > 0 && c->chunks_since_sort >= c->p.sort_every) {
+        if ((s = rebuild_sorted(c, true)) != MD_OK) return s;
+        c->chunks_since_sort = 0;
+      }
+      if ((s = capture_chunk(c)) != MD_OK) return s;
+      HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, false));
+      HIPC(c, hipGraphLaunch(c->graph, c->L.stream));
+      ++c->chunks_since_sort;
+      done += chunk;
+    } else {
+      if ((s = step_eager(c)) != MD_OK) return s;
+      ++done;
+    }
+  }
+  int32_t w[SW_WORDS];
+  if ((s = read_status(c, w)) != MD_OK) return s;
+  s = status_code(w[SW_BITS]);
+  if (s < 0) {
+    // roll back to the last clean snapshot (its step count comes with it)
+    // and rebuild the list there
+    c->cur = 0;
+    HIPC(c, hipMemsetAsync(c->status + SW_BITS, 0, sizeof(int32_t), c->L.stream));
+    HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, true));
+    md_status r = rebuild_sorted(c, true);
+    if (r == MD_OK) r = forces_now(c, false);
+    HIPC(c, hipStreamSynchronize(c->L.stream));
+    return s;
+  }
+  return s;
+}
+
+md_status md_energy(md_ctx* c, double* pe, double* ke) {
+  if (!c) return MD_E_ARG;
+  if (!c->has_state) return MD_E_ORDER;
+  md_status s;
+  if (!c->built) {
+    if ((s = rebuild_sorted(c, false)) != MD_OK) return s;
+  }
+  if ((s = forces_now(c, false)) != MD_OK) return s;
+  State& st = c->st[c->cur];
+  Geometry g = c->g;
+  if (!c->v_half) {
+    // velocities are on-step: no half-kick correction
+    g.dt = 0.0;
+  }
+  HIPC(c, launch_energy(c->L, g, st, c->t, c->energy_dev, c->n_rep));
+  std::vector<double> h(2 * (size_t)c->n_rep);
+  HIPC(c, hipMemcpyAsync(h.data(), c->energy_dev, h.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, c->L.stream));
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  for (int r = 0; r < c->n_rep; ++r) {
+    if (pe) pe[r] = h[2 * r];
+    if (ke) ke[r] = h[2 * r + 1];
+  }
+  int32_t w[SW_WORDS];
+  if ((s = read_status(c, w)) != MD_OK) return s;
+  return status_code(w[SW_BITS]);
+}
+
+md_status md_get_state(md_ctx* c, double* x, double* v, double* f) {
+  if (!c) return MD_E_ARG;
+  if (!c->has_state) return MD_E_ORDER;
+  md_status s;
+  if (c->built) {
+    if ((s = forces_now(c, true)) != MD_OK) return s;
+  } else if (f) {
+    return MD_E_ORDER;
+  }
+  const double vscale = c->v_half ? 0.5 * c->p.dt * c->g.acc : 0.0;
+  HIPC(c, launch_export(c->L, c->g, c->st[c->cur], x, v, f, nullptr, nullptr, vscale));
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  return MD_OK;
+}
+
+md_status md_compute_forces(md_ctx* c, double* f, double* rho, double* fp) {
+  if (!c) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  md_status s;
+  if ((s = forces_now(c, true)) != MD_OK) return s;
+  HIPC(c, launch_export(c->L, c->g, c->st[c->cur], nullptr, nullptr, f, rho, fp, 0.0));
+  int32_t w[SW_WORDS];
+  if ((s = read_status(c, w)) != MD_OK) return s;
+  return status_code(w[SW_BITS]);
+}
+
+md_status md_stats(md_ctx* c, md_stats_t* o) {
+  if (!c || !o) return MD_E_ARG;
+  int32_t w[SW_WORDS];
+  md_status s = read_status(c, w);
+  if (s != MD_OK) return s;
+  int64_t v64[3];
+  memcpy(&v64[0], &w[SW_STEPS], 8);
+  memcpy(&v64[1], &w[SW_REBUILDS], 8);
+  memcpy(&v64[2], &w[SW_LIST_TOTAL], 8);
+  o->steps = v64[0];
+  o->rebuilds = v64[1];
+  o->list_entries = v64[2];
+  o->max_list = w[SW_MAX_LIST];
+  o->max_cell = w[SW_MAX_CELL];
+  o->status_bits = w[SW_BITS];
+  o->reserved = 0;
+  return MD_OK;
+}
+
+md_status md_get_cells(md_ctx* c, int32_t* cell) {
+  if (!c || !cell) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  HIPC(c, launch_export_cells(c->L, c->g, c->st[c->cur], cell));
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  return MD_OK;
+}
+
+md_status md_get_neighbors(md_ctx* c, int32_t* cnt, int32_t* nbr, int32_t cap_out) {
+  if (!c || !cnt || !nbr || cap_out < 1) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  HIPC(c, launch_export_nbrs(c->L, c->g, c->st[c->cur], cnt, nbr, cap_out));
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  return MD_OK;
+}
+
+md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
+  if (!c || reps < 0 || pass < 0 || pass > 3) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  State& s = c->st[c->cur];
+  if (reps == 0) return MD_OK;
+  switch (pass) {
+    case 0:
+      for (int r = 0; r < reps; ++r)
+        HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, nullptr,
+                               nullptr, c->sz.cells, false));
+      break;
+    case 1:
+      // the kernel md_step runs, writing the other position buffer; positions,
+      // velocities and the step counter come back from a snapshot afterwards
+      HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, false));
+      for (int r = 0; r < reps; ++r)
+        HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
+                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH));
+      HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, true));
+      break;
+    case 2:
+      // list build from freshly filled bins (one binning first, bins zeroed after)
+      HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+      HIPC(c, launch_bin(c->L, c->g, s, nullptr));
+      for (int r = 0; r < reps; ++r) HIPC(c, launch_build(c->L, c->g, s, nullptr));
+      HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+      break;
+    default:
+      // binning (wraps positions and resets x_ref), then one build keeps the list consistent
+      for (int r = 0; r < reps; ++r) {
+        HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+        HIPC(c, launch_bin(c->L, c->g, s, nullptr));
+      }
+      HIPC(c, launch_build(c->L, c->g, s, nullptr));
+      HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+      break;
+  }
+  return MD_OK;
+}
+
+void md_destroy(md_ctx* c) {
+  if (!c) return;
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// md_internal.h -- device data structures, helpers and kernel launchers of
+// the MI355X EAM library.  Host API in md_api.hip, kernels in md_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdk {
+
+// ---------------------------------------------------------------- constants
+
+constexpr int kBlock = 256;          // threads per block of the per-atom passes
+constexpr int kBuildBlock = 64;      // one wave per cell in the list build
+constexpr int kMaxStage = 512;       // candidates staged in LDS per build batch
+constexpr int kMaxCellCap = 256;     // hard limit of cell_capacity
+constexpr int kMaxNbrCap = 1024;     // hard limit of nbr_capacity
+constexpr int kIndexBits = 26;       // list entry: j | image code << 26
+constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
+constexpr uint32_t kNoShift = 21u;   // code of the zero image shift: 1 | 1<<2 | 1<<4
+constexpr int kXcd = 8;              // MI355X dispatches workgroups round-robin over 8 XCDs
+
+// status word bits (device, sticky)
+constexpr int32_t ST_NBR_OVERFLOW = 1;
+constexpr int32_t ST_CELL_OVERFLOW = 2;
+constexpr int32_t ST_NONFINITE = 4;
+constexpr int32_t ST_LOST = 8;
+constexpr int32_t ST_ERR_MASK = 0xff;
+constexpr int32_t ST_RHO_RANGE = 256;
+
+// status block layout (int32 words; 64-bit counters at even word offsets)
+enum StatusWord : int {
+  SW_BITS = 0,
+  SW_FLAG0 = 1,  // rebuild request, step parity 0
+  SW_FLAG1 = 2,  // rebuild request, step parity 1
+  SW_MAX_LIST = 3,
+  SW_MAX_CELL = 4,
+  SW_SCRATCH = 5,      // throw-away flag for timing launches
+  SW_STEPS = 8,        // int64
+  SW_REBUILDS = 10,    // int64
+  SW_LIST_TOTAL = 12,  // int64
+  SW_SNAP_STEPS = 14,  // int64, SW_STEPS at the last snapshot
+  SW_WORDS = 64
+};
+
+// ---------------------------------------------------------------- structs
+
+struct RepDev {
+  double box[3];
+  double half[3];
+  double inv_cell[3];
+  int64_t atom0;
+  int32_t n_atoms;
+  int32_t cell0;
+  int32_t nc[3];
+  int32_t ncell;
+  int32_t pad[4];
+};
+
+struct AtomTile {
+  int32_t rep;
+  int32_t begin;  // global atom index of the first atom
+  int32_t count;  // atoms in this tile (0 = idle block)
+  int32_t pad;
+};
+
+struct CellTile {
+  int32_t rep;
+  int32_t cell;  // cell index within the replica (-1 = idle block)
+};
+
+// Per-segment tables in the library's own layout (built on the host).
+struct Tables {
+  const double4* rho_val;  // [nr-1] c0..c3 of rho(r)
+  const double4* phi_val;  // [nr-1] c0..c3 of phi(r)
+  const double4* dpair_a;  // [nr-1] (rho'0, rho'1, rho'2, phi'0): derivative cubics in t, pre-scaled
+  const double2* dpair_b;  // [nr-1] (phi'1, phi'2)
+  const double4* emb_val;  // [ne-1] c0..c3 of F(rho)
+  const float4* rho_val32;  // float copies for the mixed form
+  const float4* dpair_a32;
+  const float2* dpair_b32;
+  double r_inv_dx;          // knots of phi and rho share the same grid starting at 0
+  double e_x0, e_inv_dx;
+  int32_t nr, ne;           // knot counts
+  float r_inv_dx32;
+  float pad;
+};
+
+struct Geometry {
+  const RepDev* reps;
+  const AtomTile* atiles;
+  const CellTile* ctiles;
+  int64_t n;        // total atoms (ELL stride)
+  int32_t n_atiles;
+  int32_t n_ctiles;
+  int32_t nbr_cap;
+  int32_t cell_cap;
+  double rc2;       // r_cut^2
+  double rl2;       // (r_cut + skin)^2
+  double lim2;      // (skin/2)^2
+  double dt;
+  double acc;       // ftm2v / mass
+  float rc2f;
+  float pad;
+};
+
+struct State {
+  double4* pos;      // current positions, w = F'(rho_i)
+  double4* pos_alt;  // other position buffer (leap-frog ping-pong)
+  double4* vel;      // velocity (half step inside md_step)
+  double4* xref;     // positions at the last list build
+  double4* frc;      // forces when requested
+  double* rho;       // rho_i when requested
+  double* epair;     // 1/2 sum phi when requested
+  int32_t* id;       // original atom index of each slot
+  int32_t* cell_of;  // cell (within replica) of each slot at the last binning
+  uint32_t* nbr;     // ELL [cap][n]
+  int32_t* cnt;      // list length (true count, may exceed cap)
+  int32_t* bin_cnt;  // [total cells]
+  int32_t* bin_idx;  // [total cells][cell_cap]
+  int32_t* cell_start;  // [total cells + 1]
+  int32_t* status;   // SW_WORDS
+  double4* sort_pos;
+  double4* sort_vel;
+  int32_t* sort_id;
+  double* partial;   // per-atom-tile energy partials [n_atiles][2]
+};
+
+// ---------------------------------------------------------------- launchers
+
+struct Launch {
+  hipStream_t stream;
+  int32_t atile_blocks;  // blocks of the per-atom passes
+  int32_t ctile_blocks;  // blocks of the per-cell passes
+};
+
+hipError_t launch_import(const Launch& L, const Geometry& g, const State& s, const double* x,
+                         const double* v);
+hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_total);
+hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond);
+hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond);
+hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64_t n_cells_total);
+hipError_t launch_density(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                          int precision, int lpa, const double4* pos, const int32_t* cond_zero,
+                          int32_t* clear_flag, int64_t n_cells_total, bool want_rho);
+hipError_t launch_force_integrate(const Launch& L, const Geometry& g, const State& s,
+                                  const Tables& t, int precision, int lpa, const double4* pos_in,
+                                  double4* pos_out, int32_t* flag_next);
+hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                             int precision, int lpa, const double4* pos);
+hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double scale);
+hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                         double* out_pe_ke, int32_t n_rep);
+hipError_t launch_export(const Launch& L, const Geometry& g, const State& s, double* x, double* v,
+                         double* f, double* rho, double* fp, double vhalf_to_onstep);
+hipError_t launch_export_cells(const Launch& L, const Geometry& g, const State& s, int32_t* cell);
+hipError_t launch_export_nbrs(const Launch& L, const Geometry& g, const State& s, int32_t* cnt,
+                              int32_t* nbr, int32_t cap_out);
+hipError_t launch_snapshot(const Launch& L, const Geometry& g, const State& s, double4* snap_pos,
+                           double4* snap_vel, bool restore);
+
+}  // namespace mdk
