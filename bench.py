@@ -1,0 +1,264 @@
+"""Benchmark of the EAM timestep loop on one MI355X.
+
+Default workload: 128,000-atom BCC box (40^3 cells, a = 3.304 A), float64,
+300 K, skin 0.3 A, dt = 1 fs, hipGraph chunks of 100 steps; K timed steps
+after W warm-up steps.  Prints one JSON line (metric: timesteps/s, plus
+atom-steps/s, roofline of the dominant kernel, CPU-oracle baseline and the
+810,448-site float64 / mixed-precision secondary points).
+
+Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 100]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "timesteps/s and atom-steps/s, EAM BCC 128k & 810k atoms, FP64 vs mixed"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+KERNEL_SRC = os.path.join(ROOT, "paper_2405_07898_amd", "csrc", "md_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_integrate_128k_traffic.json")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def force_pass_bytes(n_atoms: int, n_l: float, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one force+integrate launch.
+
+    Per atom: x (24) + F' (8, 4 mixed) + list length (4) + list entries (4 n_l)
+    + v read and write (48) + new x (24) + x_ref (24); neighbour gathers are
+    cache-served and not counted.
+    """
+    per = 24 + (4 if mixed else 8) + 4 + 4 * n_l + 48 + 24 + 24
+    return n_atoms * per
+
+
+def force_pass_flops(n_atoms: int, n_l: float, n_int: float) -> float:
+    """Algorithmic flops (paper Table "flopmodel"): 9 per list entry (distance and
+    test), 31 per interaction (r^-1, r, segment, rho' and phi', force), 8 per atom
+    (F' sum reuse and the Verlet update)."""
+    return n_atoms * (9 * n_l + 31 * n_int + 8)
+
+
+def source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def load_traffic(n_launch_atoms: int):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != source_hash() or t.get("n_atoms") != n_launch_atoms:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_system(md, box, tabs, *, precision, chunk, lpa=0):
+    from workloads import configs, potential
+
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+                       ftm2v=configs.FTM2V, precision=precision, chunk_steps=chunk,
+                       lanes_per_atom=lpa, nbr_capacity=128, cell_capacity=64, sort_every=1)
+    s = md.System(p, tabs, [box.n], box.box[None, :])
+    s.set_state(box.x, box.v)
+    s.build_neighbors()
+    return s
+
+
+def time_steps(torch, s, steps: int) -> float:
+    """Seconds for `steps` MD steps, bracketed by stream events and syncs."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    s.stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = e0.elapsed_time(e1) * 1e-3
+    return max(ev, 1e-12), wall
+
+
+def time_kernel(torch, s, md, which: int, reps: int) -> float:
+    """Average duration (us) of one pass kernel: per-launch event pairs on the
+    library's stream."""
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    s.launch_pass(which, 2)  # warm
+    s.stream.synchronize()
+    for k in range(reps):
+        starts[k].record(s.stream)
+        s.launch_pass(which, 1)
+        ends[k].record(s.stream)
+    s.stream.synchronize()
+    d = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)]) * 1e3
+    return float(np.mean(d)), float(np.median(d))
+
+
+def cpu_baseline(box, tabs, budget_s: float = 15.0):
+    import oracle
+    from workloads import configs, potential
+
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    kw = dict(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+              ftm2v=configs.FTM2V)
+    t0 = time.perf_counter()
+    oracle.md_run(box.x, box.v, box.box, tabs, 5, **kw)
+    per = (time.perf_counter() - t0) / 5.0
+    steps = int(max(5, min(2000, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    out = oracle.md_run(box.x, box.v, box.box, tabs, steps, **kw)
+    dt = time.perf_counter() - t0
+    assert out["code"] == 0
+    return dict(value=steps / dt, unit="timesteps/s", cores=threads, kind="oracle",
+                sample=f"{steps} velocity-Verlet steps of the same {box.n}-atom float64 workload "
+                       f"(first list build included), OpenMP over atoms",
+                atom_steps_per_s=steps * box.n / dt)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--secondary-steps", type=int, default=1000)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--lpa", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the EAM path here is built and timed on a "
+              "single MI355X (multi-GPU sharding is design-only); run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2405_07898_amd import md
+    from workloads import configs, potential
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    md.lib()
+    tabs = potential.md_tables()
+    box = configs.config_128k()
+    log(f"workload 128k: n={box.n} box={box.box[0]:.3f} A; building")
+    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100, lpa=args.lpa)
+    pe0, ke0 = s.energy()
+    log(f"warmup {args.warmup} steps")
+    s.step(args.warmup)
+    st0 = s.stats()
+    log(f"timing {args.steps} steps")
+    sec, wall = time_steps(torch, s, args.steps)
+    st1 = s.stats()
+    pe1, ke1 = s.energy()
+    ts = args.steps / sec
+    n_l = st1["list_entries"] / box.n
+    log(f"{ts:.1f} timesteps/s ({sec * 1e3 / args.steps:.4f} ms/step, wall {wall:.3f} s), "
+        f"rebuilds {st1['rebuilds'] - st0['rebuilds']}, mean list {n_l:.2f}")
+
+    # dominant kernel: force + integrate, timed per launch on the library stream
+    dens_us, dens_med = time_kernel(torch, s, md, md.PASS_DENSITY, args.kernel_reps)
+    force_us, force_med = time_kernel(torch, s, md, md.PASS_FORCE_RAW, args.kernel_reps)
+    byts = force_pass_bytes(box.n, n_l, False)
+    flops = force_pass_flops(box.n, n_l, n_l)
+    gbs = byts / (force_us * 1e-6) / 1e9
+    tfl = flops / (force_us * 1e-6) / 1e12
+    # the roofline that binds: intensity below the float64 ridge -> HBM
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    bound = "hbm" if flops / byts < ridge else "alu"
+    traffic = load_traffic(box.n)
+    roof = {"bound": bound, "kernel": "k_force_integrate<fp64>",
+            "achieved": round(gbs, 1) if bound == "hbm" else round(tfl, 3),
+            "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_PEAK_TFLOPS,
+            "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+            "frac": round((gbs / HBM_PEAK_GBS) if bound == "hbm" else (tfl / FP64_PEAK_TFLOPS), 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": byts, "algorithmic_flops_per_launch": flops,
+            "avg_kernel_us": round(force_us, 3), "median_kernel_us": round(force_med, 3),
+            "alu_frac": round(tfl / FP64_PEAK_TFLOPS, 4), "mean_list_length": round(n_l, 3),
+            "density_kernel_us": round(dens_us, 3)}
+    log(f"force pass {force_us:.2f} us -> {gbs:.0f} GB/s ({roof['frac'] * 100:.1f}% HBM), "
+        f"{tfl:.2f} TFLOP/s; density {dens_us:.2f} us")
+    s.close()
+
+    out = {
+        "metric": METRIC, "value": round(ts, 2), "unit": "timesteps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3 / args.steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "EAM BCC 40x40x40 cells (128,000 atoms), a=3.304 A, 300 K, "
+                               "skin 0.3 A, dt 1 fs, NVE, float64, hipGraph chunks of 100 steps",
+                   "n_atoms": box.n, "chunk_steps": 100},
+        "atom_steps_per_s": round(ts * box.n, 1),
+        "energy_drift_per_atom_eV": float(abs((pe1[0] + ke1[0]) - (pe0[0] + ke0[0])) / box.n),
+        "rebuilds_in_timed_region": int(st1["rebuilds"] - st0["rebuilds"]),
+        "wall_s_timed": round(wall, 4),
+        "roofline": roof,
+    }
+
+    if not args.no_secondary:
+        big = configs.config_810k()
+        sec_out = {}
+        for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
+            log(f"secondary 810k {name}: n={big.n}")
+            sb = make_system(md, big, tabs, precision=prec, chunk=100, lpa=args.lpa)
+            sb.step(100)
+            t2, _ = time_steps(torch, sb, args.secondary_steps)
+            stb = sb.stats()
+            nlb = stb["list_entries"] / big.n
+            fu, _ = time_kernel(torch, sb, md, md.PASS_FORCE_RAW, 50)
+            b2 = force_pass_bytes(big.n, nlb, prec == md.MD_MIXED)
+            sec_out[name] = {"timesteps_per_s": round(args.secondary_steps / t2, 2),
+                             "atom_steps_per_s": round(args.secondary_steps / t2 * big.n, 1),
+                             "force_pass_us": round(fu, 3),
+                             "force_pass_hbm_frac": round(b2 / (fu * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                             "mean_list_length": round(nlb, 3), "rebuilds": stb["rebuilds"]}
+            if name == "fp64":
+                f64, _, _ = sb.compute_forces()
+                x64, _, _ = sb.get_state(want_f=False)
+            else:
+                # mixed forces at the float64 run's positions, against its float64 forces
+                sb.set_state(x64, torch.zeros_like(x64))
+                sb.build_neighbors()
+                fm, _, _ = sb.compute_forces()
+                err = (fm - f64).norm(dim=1)
+                rms = f64.norm(dim=1).pow(2).mean().sqrt().item()
+                sec_out[name]["force_err_vs_fp64_max_eVA"] = err.max().item()
+                sec_out[name]["force_err_vs_fp64_rms_eVA"] = err.pow(2).mean().sqrt().item()
+                sec_out[name]["force_rms_eVA"] = rms
+            sb.close()
+            log(f"  {sec_out[name]}")
+        out["secondary_810k"] = {"n_atoms": big.n, "steps": args.secondary_steps,
+                                 "workload": "74^3 BCC sites - 1% vacancies, 2500 K", **sec_out}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(box, tabs)
+        log(f"  {out['cpu_baseline']}")
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

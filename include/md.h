@@ -29,7 +29,8 @@
  *     thread-safe.
  *   - Device-side conditions are latched in a status word read at the end of
  *     md_step / md_build_neighbors.  After an error every kernel of the
- *     context becomes a no-op until md_set_state or md_restore_checkpoint.
+ *     context becomes a no-op; md_step rolls the state back to the last clean
+ *     chunk start and clears the error, md_set_state clears it too.
  */
 #ifndef MDEAM_MD_H
 #define MDEAM_MD_H
@@ -164,7 +165,10 @@ md_status md_get_neighbors(md_ctx* ctx, int32_t* cnt, int32_t* nbr, int32_t cap_
 
 /* Enqueue reps launches of one pass on the context stream, with no
  * synchronisation, for timing with events: 0 = density, 1 = force+integrate
- * (advances the state), 2 = list build, 3 = binning. */
+ * (state restored from a snapshot afterwards), 2 = list build (after one
+ * binning), 3 = binning (followed by one list build), 4 = force+integrate
+ * alone: every launch reads the same positions and advances the velocities,
+ * so the state is not usable afterwards until md_set_state. */
 md_status md_launch_pass(md_ctx* ctx, int32_t pass, int32_t reps);
 
 /* Last error text of this context (or of the library when ctx is NULL). */

@@ -151,15 +151,15 @@ struct Buffers {
   RepDev* reps;
   AtomTile* atiles;
   CellTile* ctiles;
-  double4 *rho_val, *phi_val, *dpair_a, *emb_val;
-  double2* dpair_b;
+  double4 *rho_val, *phi_val, *emb_val;
+  double2* dpair3;
   float4 *rho_val32, *dpair_a32;
   float2* dpair_b32;
   double4 *pos0, *pos1, *vel, *xref, *frc;
   double *rho, *epair;
   int32_t *id, *cell_of, *cnt;
   uint32_t* nbr;
-  int32_t *bin_cnt, *bin_idx, *cell_start, *status;
+  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *status;
   double4 *sort_pos, *sort_vel;
   int32_t* sort_id;
   double4 *snap_pos, *snap_vel;
@@ -178,8 +178,7 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.ctiles = c.take<CellTile>(s.ctile_blocks);
   o.rho_val = c.take<double4>(nr - 1);
   o.phi_val = c.take<double4>(nr - 1);
-  o.dpair_a = c.take<double4>(nr - 1);
-  o.dpair_b = c.take<double2>(nr - 1);
+  o.dpair3 = c.take<double2>(3 * (size_t)(nr - 1));
   o.emb_val = c.take<double4>(ne - 1);
   o.rho_val32 = c.take<float4>(nr - 1);
   o.dpair_a32 = c.take<float4>(nr - 1);
@@ -198,6 +197,7 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.bin_cnt = c.take<int32_t>((size_t)s.cells);
   o.bin_idx = c.take<int32_t>((size_t)s.cells * p->cell_capacity);
   o.cell_start = c.take<int32_t>((size_t)s.cells + 1);
+  o.cell_stat = c.take<int32_t>(3 * (size_t)s.cells);
   o.status = c.take<int32_t>(SW_WORDS);
   o.sort_pos = c.take<double4>(N);
   o.sort_vel = c.take<double4>(N);
@@ -311,15 +311,14 @@ md_status capture_chunk(md_ctx* c) {
 
 // Library tables from the caller's per-segment coefficients.
 void build_tables(const md_spline* phi, const md_spline* rho, const md_spline* emb,
-                  std::vector<double4>* rv, std::vector<double4>* pv, std::vector<double4>* da,
-                  std::vector<double2>* db, std::vector<double4>* ev, std::vector<float4>* rv32,
-                  std::vector<float4>* da32, std::vector<float2>* db32) {
+                  std::vector<double4>* rv, std::vector<double4>* pv, std::vector<double2>* d3,
+                  std::vector<double4>* ev, std::vector<float4>* rv32, std::vector<float4>* da32,
+                  std::vector<float2>* db32) {
   const int ns = rho->n_knots - 1;
   const double a = rho->inv_dx;
   rv->resize(ns);
   pv->resize(ns);
-  da->resize(ns);
-  db->resize(ns);
+  d3->resize(3 * (size_t)ns);
   rv32->resize(ns);
   da32->resize(ns);
   db32->resize(ns);
@@ -328,13 +327,15 @@ void build_tables(const md_spline* phi, const md_spline* rho, const md_spline* e
     const double* f = phi->coef + 4 * k;
     (*rv)[k] = make_double4(r[0], r[1], r[2], r[3]);
     (*pv)[k] = make_double4(f[0], f[1], f[2], f[3]);
-    // derivative cubics in t, pre-scaled by alpha: f'(t) = (c1 + 2 c2 t + 3 c3 t^2) alpha
-    (*da)[k] = make_double4(r[1] * a, 2.0 * r[2] * a, 3.0 * r[3] * a, f[1] * a);
-    (*db)[k] = make_double2(2.0 * f[2] * a, 3.0 * f[3] * a);
+    // derivative quadratics in t, pre-scaled by alpha: f'(t) = (c1 + 2 c2 t + 3 c3 t^2) alpha
+    const double r0 = r[1] * a, r1 = 2.0 * r[2] * a, r2 = 3.0 * r[3] * a;
+    const double p0 = f[1] * a, p1 = 2.0 * f[2] * a, p2 = 3.0 * f[3] * a;
+    (*d3)[3 * k + 0] = make_double2(r0, r1);
+    (*d3)[3 * k + 1] = make_double2(r2, p0);
+    (*d3)[3 * k + 2] = make_double2(p1, p2);
     (*rv32)[k] = make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
-    const double4 q = (*da)[k];
-    (*da32)[k] = make_float4((float)q.x, (float)q.y, (float)q.z, (float)q.w);
-    (*db32)[k] = make_float2((float)(*db)[k].x, (float)(*db)[k].y);
+    (*da32)[k] = make_float4((float)r0, (float)r1, (float)r2, (float)p0);
+    (*db32)[k] = make_float2((float)p1, (float)p2);
   }
   const int ne = emb->n_knots - 1;
   ev->resize(ne);
@@ -446,11 +447,11 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   std::vector<AtomTile> atx = xcd_order(at, AtomTile{0, 0, 0, 0});
   std::vector<CellTile> ctx = xcd_order(ct, CellTile{0, -1});
 
-  std::vector<double4> rv, pv, da, ev;
-  std::vector<double2> db;
+  std::vector<double4> rv, pv, ev;
+  std::vector<double2> d3;
   std::vector<float4> rv32, da32;
   std::vector<float2> db32;
-  build_tables(phi, rho, emb, &rv, &pv, &da, &db, &ev, &rv32, &da32, &db32);
+  build_tables(phi, rho, emb, &rv, &pv, &d3, &ev, &rv32, &da32, &db32);
 
 #define UP(dst, vec)                                                                          \
   do {                                                                                        \
@@ -466,8 +467,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   UP(b.ctiles, ctx);
   UP(b.rho_val, rv);
   UP(b.phi_val, pv);
-  UP(b.dpair_a, da);
-  UP(b.dpair_b, db);
+  UP(b.dpair3, d3);
   UP(b.emb_val, ev);
   UP(b.rho_val32, rv32);
   UP(b.dpair_a32, da32);
@@ -476,6 +476,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   hipError_t e = hipMemset(b.status, 0, SW_WORDS * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.bin_cnt, 0, (size_t)ls.cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.cnt, 0, (size_t)ls.n * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(b.cell_stat, 0, 3 * (size_t)ls.cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.frc, 0, (size_t)ls.n * sizeof(double4));
   if (e != hipSuccess) {
     md_status r_ = hip_fail(c, e, "hipMemset");
@@ -502,8 +503,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   Tables& t = c->t;
   t.rho_val = b.rho_val;
   t.phi_val = b.phi_val;
-  t.dpair_a = b.dpair_a;
-  t.dpair_b = b.dpair_b;
+  t.dpair3 = b.dpair3;
   t.emb_val = b.emb_val;
   t.rho_val32 = b.rho_val32;
   t.dpair_a32 = b.dpair_a32;
@@ -514,6 +514,32 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   t.e_inv_dx = emb->inv_dx;
   t.nr = rho->n_knots;
   t.ne = emb->n_knots;
+
+  // persistent pair passes: one workgroup per CU, a multiple of the XCD count
+  {
+    int dev = 0, cus = 0, lds_max = 0;
+    hipError_t e2 = hipGetDevice(&dev);
+    if (e2 == hipSuccess) e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e2 == hipSuccess)
+      e2 = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e2 != hipSuccess) {
+      md_status r_ = hip_fail(c, e2, "device attributes");
+      delete c;
+      return r_;
+    }
+    c->L.persist_blocks = std::max(kXcd, (cus / kXcd) * kXcd);
+    if (force_lds_bytes(t, p->precision) > (size_t)lds_max ||
+        density_lds_bytes(t, p->precision) > (size_t)lds_max) {
+      delete c;
+      return MD_E_TABLE;
+    }
+    e2 = allow_pair_lds(t, p->precision);
+    if (e2 != hipSuccess) {
+      md_status r_ = hip_fail(c, e2, "hipFuncSetAttribute");
+      delete c;
+      return r_;
+    }
+  }
 
   State base{};
   base.vel = b.vel;
@@ -528,6 +554,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   base.bin_cnt = b.bin_cnt;
   base.bin_idx = b.bin_idx;
   base.cell_start = b.cell_start;
+  base.cell_stat = b.cell_stat;
   base.status = b.status;
   base.sort_pos = b.sort_pos;
   base.sort_vel = b.sort_vel;
@@ -678,6 +705,7 @@ md_status md_compute_forces(md_ctx* c, double* f, double* rho, double* fp) {
 
 md_status md_stats(md_ctx* c, md_stats_t* o) {
   if (!c || !o) return MD_E_ARG;
+  HIPC(c, launch_cell_stats(c->L, c->st[c->cur], c->sz.cells));
   int32_t w[SW_WORDS];
   md_status s = read_status(c, w);
   if (s != MD_OK) return s;
@@ -712,7 +740,7 @@ md_status md_get_neighbors(md_ctx* c, int32_t* cnt, int32_t* nbr, int32_t cap_ou
 }
 
 md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
-  if (!c || reps < 0 || pass < 0 || pass > 3) return MD_E_ARG;
+  if (!c || reps < 0 || pass < 0 || pass > 4) return MD_E_ARG;
   if (!c->built) return MD_E_ORDER;
   State& s = c->st[c->cur];
   if (reps == 0) return MD_OK;
@@ -730,6 +758,13 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
         HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
                                        c->st[1 - c->cur].pos, c->status + SW_SCRATCH));
       HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, true));
+      break;
+    case 4:
+      // the same kernel with no snapshot around it: velocities advance on every
+      // launch while positions are read from the unchanged current buffer
+      for (int r = 0; r < reps; ++r)
+        HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
+                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH));
       break;
     case 2:
       // list build from freshly filled bins (one binning first, bins zeroed after)

@@ -72,8 +72,8 @@ struct CellTile {
 struct Tables {
   const double4* rho_val;  // [nr-1] c0..c3 of rho(r)
   const double4* phi_val;  // [nr-1] c0..c3 of phi(r)
-  const double4* dpair_a;  // [nr-1] (rho'0, rho'1, rho'2, phi'0): derivative cubics in t, pre-scaled
-  const double2* dpair_b;  // [nr-1] (phi'1, phi'2)
+  const double2* dpair3;   // [nr-1][3]: (rho'0, rho'1), (rho'2, phi'0), (phi'1, phi'2):
+                           // derivative quadratics in t, pre-scaled by 1/dx
   const double4* emb_val;  // [ne-1] c0..c3 of F(rho)
   const float4* rho_val32;  // float copies for the mixed form
   const float4* dpair_a32;
@@ -118,6 +118,7 @@ struct State {
   int32_t* bin_cnt;  // [total cells]
   int32_t* bin_idx;  // [total cells][cell_cap]
   int32_t* cell_start;  // [total cells + 1]
+  int32_t* cell_stat;   // [total cells][3]: longest list, list entries, atoms (last build)
   int32_t* status;   // SW_WORDS
   double4* sort_pos;
   double4* sort_vel;
@@ -131,11 +132,13 @@ struct Launch {
   hipStream_t stream;
   int32_t atile_blocks;  // blocks of the per-atom passes
   int32_t ctile_blocks;  // blocks of the per-cell passes
+  int32_t persist_blocks;  // workgroups of the persistent pair passes (CU count, multiple of 8)
 };
 
 hipError_t launch_import(const Launch& L, const Geometry& g, const State& s, const double* x,
                          const double* v);
 hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_total);
+hipError_t launch_cell_stats(const Launch& L, const State& s, int64_t n_cells_total);
 hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond);
 hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond);
 hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64_t n_cells_total);
@@ -147,6 +150,9 @@ hipError_t launch_force_integrate(const Launch& L, const Geometry& g, const Stat
                                   double4* pos_out, int32_t* flag_next);
 hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                              int precision, int lpa, const double4* pos);
+size_t density_lds_bytes(const Tables& t, int precision);
+size_t force_lds_bytes(const Tables& t, int precision);
+hipError_t allow_pair_lds(const Tables& t, int precision);
 hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double scale);
 hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                          double* out_pe_ke, int32_t n_rep);

@@ -64,9 +64,10 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
   return v;
 }
 
+// Errors latched by earlier kernels (plain load: kernel boundaries make
+// them visible; errors raised inside the running kernel are not waited for).
 __device__ __forceinline__ bool has_error(const int32_t* status) {
-  return (__hip_atomic_load(status + SW_BITS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-          ST_ERR_MASK) != 0;
+  return (status[SW_BITS] & ST_ERR_MASK) != 0;
 }
 
 __device__ __forceinline__ void set_bits(int32_t* status, int32_t bits) {
@@ -176,12 +177,7 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ p, int64
 __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* cond) {
   if (cond && *cond == 0) return;
   if (has_error(s.status)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (cond) *counter64(s.status, SW_REBUILDS) += 1ull;
-    s.status[SW_MAX_LIST] = 0;
-    s.status[SW_MAX_CELL] = 0;
-    *counter64(s.status, SW_LIST_TOTAL) = 0ull;
-  }
+  if (cond && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
   const AtomTile tl = g.atiles[blockIdx.x];
   if ((int)threadIdx.x >= tl.count) return;
   const RepDev& rp = g.reps[tl.rep];
@@ -215,23 +211,33 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
 
 // ============================================================ list build
 
-// One wave per cell.  The atoms of the 27 surrounding cells are staged in LDS
-// (each cell ordered by atom index, so the candidate order is deterministic,
-// Sec. III-C), then every atom of the centre cell scans them 64 at a time;
-// admitted candidates (r^2 < (r_cut+skin)^2 under the minimum image, same
-// expression order as the reference) are compacted with a ballot and written
-// to the ELL list together with their image shift.
+// One wave per cell.  The atoms of the 27 surrounding cells are gathered,
+// each cell ordered by atom index (a deterministic candidate order,
+// Sec. III-C), into registers: lane l holds candidates l, l+64, ... .  Every
+// atom of the centre cell then tests all candidates against
+// r^2 < (r_cut+skin)^2 and compacts the admitted ones with a ballot into its
+// ELL row, each entry carrying its image shift.
+//
+// The shift of a candidate is that of its stencil cell (a wrapped cell index
+// means one box length).  For every pair within the list radius this is the
+// minimum image, and d = fma(s, L, x_j - x_i) rounds exactly like the
+// reference's x_j - x_i followed by -L / +L, so the admitted set is
+// bit-identical to the reference's; pairs at other images are farther than the
+// list radius under either rule.
+constexpr int kBuildChunks = kMaxStage / 64;
+
 __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t* cond) {
   if (cond && *cond == 0) return;
   if (has_error(s.status)) return;
   const CellTile ct = g.ctiles[blockIdx.x];
   if (ct.cell < 0) return;
   const RepDev& rp = g.reps[ct.rep];
-  __shared__ int32_t s_q[27], s_n[27], s_off[28];
+  __shared__ int32_t s_q[27], s_n[27], s_off[28], s_code[27];
   __shared__ int32_t s_raw[kMaxStage];
   __shared__ int32_t s_idx[kMaxStage];
-  __shared__ double s_x[kMaxStage], s_y[kMaxStage], s_z[kMaxStage];
+  __shared__ int8_t s_cell[kMaxStage];
   __shared__ int32_t s_center[kMaxCellCap], s_base[kMaxCellCap];
+  __shared__ double s_cx[kMaxCellCap], s_cy[kMaxCellCap], s_cz[kMaxCellCap];
   const int lane = threadIdx.x;
   const int32_t nx = rp.nc[0], ny = rp.nc[1], nz = rp.nc[2];
   const int32_t c = ct.cell;
@@ -239,12 +245,17 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
   const int32_t ccap = g.cell_cap;
   if (lane < 27) {
     const int dz = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dx = lane % 3 - 1;
-    const int32_t qx = (cx + dx + nx) % nx, qy = (cy + dy + ny) % ny, qz = (cz + dz + nz) % nz;
-    const int32_t q = rp.cell0 + (qz * ny + qy) * nx + qx;
+    const int32_t ux = cx + dx, uy = cy + dy, uz = cz + dz;
+    // wrapped index below 0: candidate near L, shift -L (code 0); above: +L (code 2)
+    const uint32_t kx = ux < 0 ? 0u : (ux >= nx ? 2u : 1u);
+    const uint32_t ky = uy < 0 ? 0u : (uy >= ny ? 2u : 1u);
+    const uint32_t kz = uz < 0 ? 0u : (uz >= nz ? 2u : 1u);
+    const int32_t q = rp.cell0 + (((uz + nz) % nz) * ny + (uy + ny) % ny) * nx + (ux + nx) % nx;
     int32_t n = s.bin_cnt[q];
     if (n > ccap) n = ccap;
     s_q[lane] = q;
     s_n[lane] = n;
+    s_code[lane] = (int32_t)(kx | (ky << 2) | (kz << 4));
   }
   __syncthreads();
   if (lane == 0) {
@@ -252,7 +263,7 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
     for (int k = 0; k < 27; ++k) s_off[k + 1] = s_off[k] + s_n[k];
   }
   __syncthreads();
-  // centre atoms in increasing index
+  // centre atoms in increasing index, with their positions
   const int32_t qc = s_q[13], n_c = s_n[13];
   for (int u = lane; u < n_c; u += 64) s_raw[u] = s.bin_idx[(int64_t)qc * ccap + u];
   __syncthreads();
@@ -260,12 +271,15 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
     const int32_t e = s_raw[u];
     int r = 0;
     for (int w = 0; w < n_c; ++w) r += (s_raw[w] < e);
+    const double4 q = s.pos[e];
     s_center[r] = e;
     s_base[r] = 0;
+    s_cx[r] = q.x;
+    s_cy[r] = q.y;
+    s_cz[r] = q.z;
   }
   __syncthreads();
   const double Lx = rp.box[0], Ly = rp.box[1], Lz = rp.box[2];
-  const double hx = rp.half[0], hy = rp.half[1], hz = rp.half[2];
   const double rl2 = g.rl2;
   const int64_t N = g.n;
   const int32_t cap = g.nbr_cap;
@@ -280,50 +294,58 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
       int sc = s0;
       while (s_off[sc + 1] <= gs) ++sc;
       s_raw[p] = s.bin_idx[(int64_t)s_q[sc] * ccap + (gs - s_off[sc])];
+      s_cell[p] = (int8_t)sc;
     }
     __syncthreads();
     for (int p = lane; p < T; p += 64) {
-      const int gs = base_off + p;
-      int sc = s0;
-      while (s_off[sc + 1] <= gs) ++sc;
+      const int sc = s_cell[p];
       const int lo = s_off[sc] - base_off, n = s_n[sc];
       const int32_t e = s_raw[p];
       int r = 0;
       for (int w = lo; w < lo + n; ++w) r += (s_raw[w] < e);
-      const int dst = lo + r;
-      const double4 q = s.pos[e];
-      s_idx[dst] = e;
-      s_x[dst] = q.x;
-      s_y[dst] = q.y;
-      s_z[dst] = q.z;
+      s_idx[lo + r] = e;
     }
     __syncthreads();
+    // candidates into registers (s_cell is per stencil cell, unchanged by the sort)
+    double px[kBuildChunks], py[kBuildChunks], pz[kBuildChunks];
+    double sx[kBuildChunks], sy[kBuildChunks], sz[kBuildChunks];
+    uint32_t ent[kBuildChunks];
+#pragma unroll
+    for (int k = 0; k < kBuildChunks; ++k) {
+      const int p = k * 64 + lane;
+      px[k] = py[k] = pz[k] = 0.0;
+      sx[k] = sy[k] = sz[k] = 0.0;
+      ent[k] = 0xffffffffu;
+      if (p < T) {
+        const int32_t j = s_idx[p];
+        const uint32_t code = (uint32_t)s_code[s_cell[p]];
+        const double4 q = s.pos[j];
+        px[k] = q.x;
+        py[k] = q.y;
+        pz[k] = q.z;
+        sx[k] = (double)((int)(code & 3u) - 1);
+        sy[k] = (double)((int)((code >> 2) & 3u) - 1);
+        sz[k] = (double)((int)(code >> 4) - 1);
+        ent[k] = (uint32_t)j | (code << kIndexBits);
+      }
+    }
     for (int u = 0; u < n_c; ++u) {
       const int32_t i = s_center[u];
-      const double4 pi = s.pos[i];
+      const double qx = s_cx[u], qy = s_cy[u], qz = s_cz[u];
       int base = s_base[u];
-      for (int p0 = 0; p0 < T; p0 += 64) {
-        const int p = p0 + lane;
-        bool ok = false;
-        uint32_t entry = 0;
-        if (p < T) {
-          const int32_t j = s_idx[p];
-          if (j != i) {
-            double dx = s_x[p] - pi.x, dy = s_y[p] - pi.y, dz = s_z[p] - pi.z;
-            uint32_t kx = 1, ky = 1, kz = 1;
-            if (dx > hx) { dx -= Lx; kx = 0; } else if (dx < -hx) { dx += Lx; kx = 2; }
-            if (dy > hy) { dy -= Ly; ky = 0; } else if (dy < -hy) { dy += Ly; ky = 2; }
-            if (dz > hz) { dz -= Lz; kz = 0; } else if (dz < -hz) { dz += Lz; kz = 2; }
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
-            ok = r2 < rl2;
-            entry = (uint32_t)j | ((kx | (ky << 2) | (kz << 4)) << kIndexBits);
-          }
-        }
+#pragma unroll
+      for (int k = 0; k < kBuildChunks; ++k) {
+        if (k * 64 >= T) break;
+        const double dx = fma(sx[k], Lx, px[k] - qx);
+        const double dy = fma(sy[k], Ly, py[k] - qy);
+        const double dz = fma(sz[k], Lz, pz[k] - qz);
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        const bool ok = ent[k] != 0xffffffffu && (int32_t)(ent[k] & kIndexMask) != i && r2 < rl2;
         const unsigned long long m = __ballot(ok);
         if (ok) {
-          const int k = base + (int)__builtin_amdgcn_mbcnt_hi(
-                                   (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (k < cap) s.nbr[(int64_t)k * N + i] = entry;
+          const int kk = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (kk < cap) s.nbr[(int64_t)kk * N + i] = ent[k];
         }
         base += __popcll(m);
       }
@@ -343,11 +365,45 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
   mx = wave_max_i32(mx);
   tot = wave_sum_i64(tot);
   if (lane == 0) {
+    // per-cell statistics (reduced on demand); the status word is only
+    // touched in the rare overflow cases
+    const int32_t full = s.bin_cnt[qc];
+    s.cell_stat[3 * (int64_t)qc + 0] = mx;
+    s.cell_stat[3 * (int64_t)qc + 1] = (int32_t)tot;
+    s.cell_stat[3 * (int64_t)qc + 2] = full;
     if (mx > cap) set_bits(s.status, ST_NBR_OVERFLOW);
-    if (s.bin_cnt[qc] > ccap) set_bits(s.status, ST_CELL_OVERFLOW);
-    atomicMax(&s.status[SW_MAX_LIST], mx);
-    atomicMax(&s.status[SW_MAX_CELL], s.bin_cnt[qc]);
-    atomicAdd(counter64(s.status, SW_LIST_TOTAL), (unsigned long long)tot);
+    if (full > ccap) set_bits(s.status, ST_CELL_OVERFLOW);
+  }
+}
+
+// Fixed-order reduction of the per-cell build statistics into the status
+// block (longest list, fullest cell, total list entries).
+__global__ __launch_bounds__(1024) void k_cell_stats(State s, int64_t m) {
+  __shared__ int32_t s_mx[1024], s_mc[1024];
+  __shared__ long long s_tot[1024];
+  int32_t mx = 0, mc = 0;
+  long long tot = 0;
+  for (int64_t c = threadIdx.x; c < m; c += 1024) {
+    mx = max(mx, s.cell_stat[3 * c + 0]);
+    tot += s.cell_stat[3 * c + 1];
+    mc = max(mc, s.cell_stat[3 * c + 2]);
+  }
+  s_mx[threadIdx.x] = mx;
+  s_mc[threadIdx.x] = mc;
+  s_tot[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s_mx[threadIdx.x] = max(s_mx[threadIdx.x], s_mx[threadIdx.x + o]);
+      s_mc[threadIdx.x] = max(s_mc[threadIdx.x], s_mc[threadIdx.x + o]);
+      s_tot[threadIdx.x] += s_tot[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s.status[SW_MAX_LIST] = s_mx[0];
+    s.status[SW_MAX_CELL] = s_mc[0];
+    *counter64(s.status, SW_LIST_TOTAL) = (unsigned long long)s_tot[0];
   }
 }
 
@@ -443,14 +499,132 @@ __device__ __forceinline__ double lane_sum_sym(double v) {
   return v;
 }
 
+// Neighbours are processed in batches of kBatch per lane: the list entries of
+// a batch are loaded together, then all their positions, then all their table
+// rows, so each batch pays the list -> position -> table latency chain once.
+constexpr int kBatch = 4;
+
+// The spline rows of a pass live in LDS for the whole kernel: one persistent
+// workgroup per CU loads them once, then walks its atom tiles.  Workgroup w
+// takes tile-table entries w, w + G, w + 2G, ... (G = grid size, a multiple of
+// the XCD count), i.e. only tiles the tile table placed on its own XCD.
+struct TileWalk {
+  int tpi;  // tiles per iteration
+  int q;    // this thread's tile slot
+  int a;    // atom within the tile
+  int sub;  // lane within the atom
+};
+
+template <int LPA>
+__device__ __forceinline__ TileWalk tile_walk() {
+  TileWalk w;
+  w.tpi = (int)blockDim.x / (64 * LPA);
+  w.q = (int)threadIdx.x / (64 * LPA);
+  const int r = (int)threadIdx.x - w.q * 64 * LPA;
+  w.a = r / LPA;
+  w.sub = r % LPA;
+  return w;
+}
+
+template <class T>
+__device__ __forceinline__ void lds_fill(T* dst, const T* __restrict__ src, int n) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+}
+
+template <int LPA>
+__device__ __forceinline__ void load_entries(const uint32_t* __restrict__ lst, int64_t N, int k0,
+                                             int m, uint32_t self_e, uint32_t (&e)[kBatch],
+                                             bool (&v)[kBatch]) {
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    const int k = k0 + u * LPA;
+    v[u] = k < m;
+    e[u] = v[u] ? lst[(int64_t)k * N] : self_e;
+  }
+}
+
+__device__ __forceinline__ void separation(uint32_t e, const RepDev& rp, double qx, double qy,
+                                           double qz, double px, double py, double pz, double& dx,
+                                           double& dy, double& dz) {
+  dx = qx - px;
+  dy = qy - py;
+  dz = qz - pz;
+  const uint32_t code = e >> kIndexBits;
+  if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
+}
+
+// rho_i of one atom (its lane's share), table rows from LDS.
+template <int PREC, int LPA>
+__device__ __forceinline__ double density_of(const Geometry& g, const State& s, const Tables& t,
+                                             const RepDev& rp, const double4* __restrict__ pos,
+                                             const void* lds_tab, int64_t i, int m, int sub) {
+  const int64_t N = g.n;
+  const double2 pxy = *reinterpret_cast<const double2*>(&pos[i]);
+  const double pz = pos[i].z;
+  const uint32_t* __restrict__ lst = s.nbr + i;
+  const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
+  const int last = t.nr - 2;
+  double acc = 0.0;
+  float sum = 0.0f, comp = 0.0f;
+  for (int k0 = sub; k0 < m; k0 += LPA * kBatch) {
+    uint32_t e[kBatch];
+    bool v[kBatch];
+    load_entries<LPA>(lst, N, k0, m, self_e, e, v);
+    double2 qxy[kBatch];
+    double qz[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const uint32_t j = e[u] & kIndexMask;
+      qxy[u] = *reinterpret_cast<const double2*>(&pos[j]);
+      qz[u] = pos[j].z;
+    }
+    if (PREC == 0) {
+      const double4* tab = reinterpret_cast<const double4*>(lds_tab);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        double dx, dy, dz;
+        separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const bool in = v[u] && r2 < g.rc2;
+        const double rr = in ? r2 : 1.0;
+        const double x = (rr * rsq64(rr)) * t.r_inv_dx;
+        const int kk = min(max((int)x, 0), last);
+        const double tt = x - (double)kk;
+        const double4 c = tab[kk];
+        if (in) acc += fma(fma(fma(c.w, tt, c.z), tt, c.y), tt, c.x);
+      }
+    } else {
+      const float4* tab = reinterpret_cast<const float4*>(lds_tab);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        double dx, dy, dz;
+        separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
+        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        const float r2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
+        const bool in = v[u] && r2 < g.rc2f;
+        const float rr = in ? r2 : 1.0f;
+        const float x = (rr * __builtin_amdgcn_rsqf(rr)) * t.r_inv_dx32;
+        const int kk = min(max((int)x, 0), last);
+        const float tt = x - (float)kk;
+        const float4 c = tab[kk];
+        if (in) two_sum_acc(sum, comp, fmaf(fmaf(fmaf(c.w, tt, c.z), tt, c.y), tt, c.x));
+      }
+    }
+  }
+  if (PREC == 0) return lane_sum_sym<LPA>(acc);
+  lane_sum2<LPA>(sum, comp);
+  return (double)sum + (double)comp;
+}
+
 // rho_i = sum_{j in list, r^2 < rc^2} rho(r_ij); F'_i stored in pos[i].w.
 // Side jobs used inside the step graph: clear the next step's rebuild flag,
 // and zero the bins after a rebuild (cond_zero set).
 template <int PREC, int LPA>
-__global__ __launch_bounds__(64 * LPA) void k_density(Geometry g, State s, Tables t,
-                                                      double4* __restrict__ pos,
-                                                      const int32_t* cond_zero, int32_t* clear_flag,
-                                                      int64_t ncells, int want_rho) {
+__global__ __launch_bounds__(1024) void k_density(Geometry g, State s, Tables t,
+                                                  double4* __restrict__ pos,
+                                                  const int32_t* cond_zero, int32_t* clear_flag,
+                                                  int64_t ncells, int want_rho) {
+  extern __shared__ double4 lds_d4[];
   if (clear_flag && blockIdx.x == 0 && threadIdx.x == 0) *clear_flag = 0;
   if (cond_zero && *cond_zero) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncells;
@@ -458,145 +632,115 @@ __global__ __launch_bounds__(64 * LPA) void k_density(Geometry g, State s, Table
       s.bin_cnt[k] = 0;
   }
   if (has_error(s.status)) return;
-  const AtomTile tl = g.atiles[blockIdx.x];
-  const int a = threadIdx.x / LPA, sub = threadIdx.x % LPA;
-  const bool active = a < tl.count;
-  const RepDev& rp = g.reps[tl.rep];
-  const int64_t i = tl.begin + (active ? a : 0);
-  const int64_t N = g.n;
-  const double2 pxy = *reinterpret_cast<const double2*>(&pos[i]);
-  const double pz = pos[i].z;
-  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-  const uint32_t* __restrict__ lst = s.nbr + i;
-  const int last = t.nr - 2;
-  double rho_i;
-  if (PREC == 0) {
-    double acc = 0.0;
-    for (int k = sub; k < m; k += LPA) {
-      const uint32_t e = lst[(int64_t)k * N];
-      const uint32_t j = e & kIndexMask;
-      const double2 qxy = *reinterpret_cast<const double2*>(&pos[j]);
-      double dx = qxy.x - pxy.x, dy = qxy.y - pxy.y, dz = pos[j].z - pz;
-      const uint32_t code = e >> kIndexBits;
-      if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      if (r2 < g.rc2) {
-        const double r = r2 * rsq64(r2);
-        const double x = r * t.r_inv_dx;
-        const int kk = min(max((int)x, 0), last);
-        const double tt = x - (double)kk;
-        const double4 c = t.rho_val[kk];
-        acc += fma(fma(fma(c.w, tt, c.z), tt, c.y), tt, c.x);
-      }
-    }
-    rho_i = lane_sum_sym<LPA>(acc);
-  } else {
-    float sum = 0.0f, comp = 0.0f;
-    const float a32 = t.r_inv_dx32;
-    for (int k = sub; k < m; k += LPA) {
-      const uint32_t e = lst[(int64_t)k * N];
-      const uint32_t j = e & kIndexMask;
-      const double2 qxy = *reinterpret_cast<const double2*>(&pos[j]);
-      double dx = qxy.x - pxy.x, dy = qxy.y - pxy.y, dz = pos[j].z - pz;
-      const uint32_t code = e >> kIndexBits;
-      if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
-      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-      const float r2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
-      if (r2 < g.rc2f) {
-        const float r = r2 * __builtin_amdgcn_rsqf(r2);
-        const float x = r * a32;
-        const int kk = min(max((int)x, 0), last);
-        const float tt = x - (float)kk;
-        const float4 c = t.rho_val32[kk];
-        two_sum_acc(sum, comp, fmaf(fmaf(fmaf(c.w, tt, c.z), tt, c.y), tt, c.x));
-      }
-    }
-    lane_sum2<LPA>(sum, comp);
-    rho_i = (double)sum + (double)comp;
+  if (PREC == 0) lds_fill(lds_d4, t.rho_val, t.nr - 1);
+  else lds_fill(reinterpret_cast<float4*>(lds_d4), t.rho_val32, t.nr - 1);
+  __syncthreads();
+  const TileWalk w = tile_walk<LPA>();
+  for (int64_t it = w.q;; it += w.tpi) {
+    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
+    if (b >= g.n_atiles) break;
+    const AtomTile tl = g.atiles[b];
+    const bool active = w.a < tl.count;
+    const RepDev& rp = g.reps[tl.rep];
+    const int64_t i = tl.begin + (active ? w.a : 0);
+    const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+    const double rho_i = density_of<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, m, w.sub);
+    if (!active || w.sub != 0) continue;
+    // F'(rho_i) from the embedding table (float64 for both forms)
+    const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
+    const int le = t.ne - 2;
+    const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
+    const double te = xe - (double)ke;
+    const double4 ce = t.emb_val[ke];
+    double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
+    if (PREC != 0) fp = (double)(float)fp;
+    pos[i].w = fp;
+    if (want_rho) s.rho[i] = rho_i;
+    if (xe > (double)(t.ne - 1)) set_bits(s.status, ST_RHO_RANGE);
   }
-  if (!active || sub != 0) return;
-  // F'(rho_i) from the embedding table (float64 for both forms)
-  const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
-  const int le = t.ne - 2;
-  const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
-  const double te = xe - (double)ke;
-  const double4 ce = t.emb_val[ke];
-  double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
-  if (PREC != 0) fp = (double)(float)fp;
-  pos[i].w = fp;
-  if (want_rho) s.rho[i] = rho_i;
-  if (xe > (double)(t.ne - 1)) set_bits(s.status, ST_RHO_RANGE);
 }
 
 // ============================================================ force pass
 
-// F_i = sum_j [(F'_i + F'_j) rho'(r) + phi'(r)] (x_j - x_i)/r   (Eq. EAMforce)
+// F_i = sum_j [(F'_i + F'_j) rho'(r) + phi'(r)] (x_j - x_i)/r   (Eq. EAMforce),
+// derivative rows from LDS (float64: 3 double2 per segment; mixed: float4 +
+// float2 arrays).
 template <int PREC, int LPA>
 __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, const Tables& t,
                                             const RepDev& rp, const double4* __restrict__ pos,
-                                            int64_t i, int m, int sub, double4 pi, double& fx,
-                                            double& fy, double& fz) {
+                                            const void* lds_tab, int64_t i, int m, int sub,
+                                            double4 pi, double& fx, double& fy, double& fz) {
   const uint32_t* __restrict__ lst = s.nbr + i;
   const int64_t N = g.n;
   const int last = t.nr - 2;
-  if (PREC == 0) {
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int k = sub; k < m; k += LPA) {
-      const uint32_t e = lst[(int64_t)k * N];
-      const uint32_t j = e & kIndexMask;
-      const double4 q = pos[j];
-      double dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
-      const uint32_t code = e >> kIndexBits;
-      if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      if (r2 < g.rc2) {
-        const double rinv = rsq64(r2);
-        const double r = r2 * rinv;
-        const double x = r * t.r_inv_dx;
+  const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
+  const float fpi = (float)pi.w;
+  for (int k0 = sub; k0 < m; k0 += LPA * kBatch) {
+    uint32_t e[kBatch];
+    bool v[kBatch];
+    load_entries<LPA>(lst, N, k0, m, self_e, e, v);
+    double4 q[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) q[u] = pos[e[u] & kIndexMask];
+    if (PREC == 0) {
+      const double2* tab = reinterpret_cast<const double2*>(lds_tab);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        double dx, dy, dz;
+        separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const bool in = v[u] && r2 < g.rc2;
+        const double rr = in ? r2 : 1.0;
+        const double rinv = rsq64(rr);
+        const double x = (rr * rinv) * t.r_inv_dx;
         const int kk = min(max((int)x, 0), last);
         const double tt = x - (double)kk;
-        const double4 A = t.dpair_a[kk];
-        const double2 B = t.dpair_b[kk];
-        const double drho = fma(fma(A.z, tt, A.y), tt, A.x);
-        const double dphi = fma(fma(B.y, tt, B.x), tt, A.w);
-        const double sc = fma(pi.w + q.w, drho, dphi) * rinv;
-        ax = fma(sc, dx, ax);
-        ay = fma(sc, dy, ay);
-        az = fma(sc, dz, az);
+        const double2 r0 = tab[3 * kk], r1 = tab[3 * kk + 1], r2v = tab[3 * kk + 2];
+        // r0 = (rho'0, rho'1), r1 = (rho'2, phi'0), r2v = (phi'1, phi'2)
+        const double drho = fma(fma(r1.x, tt, r0.y), tt, r0.x);
+        const double dphi = fma(fma(r2v.y, tt, r2v.x), tt, r1.y);
+        const double sc = fma(pi.w + q[u].w, drho, dphi) * rinv;
+        if (in) {
+          ax = fma(sc, dx, ax);
+          ay = fma(sc, dy, ay);
+          az = fma(sc, dz, az);
+        }
+      }
+    } else {
+      const float4* ta = reinterpret_cast<const float4*>(lds_tab);
+      const float2* tb = reinterpret_cast<const float2*>(ta + (t.nr - 1));
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        double dx, dy, dz;
+        separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
+        const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
+        const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+        const bool in = v[u] && r2 < g.rc2f;
+        const float rr = in ? r2 : 1.0f;
+        const float rinv = __builtin_amdgcn_rsqf(rr);
+        const float x = (rr * rinv) * t.r_inv_dx32;
+        const int kk = min(max((int)x, 0), last);
+        const float tt = x - (float)kk;
+        const float4 A = ta[kk];
+        const float2 B = tb[kk];
+        const float drho = fmaf(fmaf(A.z, tt, A.y), tt, A.x);
+        const float dphi = fmaf(fmaf(B.y, tt, B.x), tt, A.w);
+        const float sc = fmaf(fpi + (float)q[u].w, drho, dphi) * rinv;
+        if (in) {
+          two_sum_acc(sx, cx, sc * ex);
+          two_sum_acc(sy, cy, sc * ey);
+          two_sum_acc(sz, cz, sc * ez);
+        }
       }
     }
+  }
+  if (PREC == 0) {
     fx = lane_sum_sym<LPA>(ax);
     fy = lane_sum_sym<LPA>(ay);
     fz = lane_sum_sym<LPA>(az);
   } else {
-    float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
-    const float a32 = t.r_inv_dx32;
-    const float fpi = (float)pi.w;
-    for (int k = sub; k < m; k += LPA) {
-      const uint32_t e = lst[(int64_t)k * N];
-      const uint32_t j = e & kIndexMask;
-      const double4 q = pos[j];
-      double dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
-      const uint32_t code = e >> kIndexBits;
-      if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
-      const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
-      const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-      if (r2 < g.rc2f) {
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float r = r2 * rinv;
-        const float x = r * a32;
-        const int kk = min(max((int)x, 0), last);
-        const float tt = x - (float)kk;
-        const float4 A = t.dpair_a32[kk];
-        const float2 B = t.dpair_b32[kk];
-        const float drho = fmaf(fmaf(A.z, tt, A.y), tt, A.x);
-        const float dphi = fmaf(fmaf(B.y, tt, B.x), tt, A.w);
-        const float sc = fmaf(fpi + (float)q.w, drho, dphi) * rinv;
-        two_sum_acc(sx, cx, sc * ex);
-        two_sum_acc(sy, cy, sc * ey);
-        two_sum_acc(sz, cz, sc * ez);
-      }
-    }
     lane_sum2<LPA>(sx, cx);
     lane_sum2<LPA>(sy, cy);
     lane_sum2<LPA>(sz, cz);
@@ -606,66 +750,96 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
   }
 }
 
+template <int PREC>
+__device__ __forceinline__ void fill_force_table(void* lds, const Tables& t) {
+  if (PREC == 0) {
+    lds_fill(reinterpret_cast<double2*>(lds), t.dpair3, 3 * (t.nr - 1));
+  } else {
+    float4* ta = reinterpret_cast<float4*>(lds);
+    lds_fill(ta, t.dpair_a32, t.nr - 1);
+    lds_fill(reinterpret_cast<float2*>(ta + (t.nr - 1)), t.dpair_b32, t.nr - 1);
+  }
+}
+
 // Force pass fused with the leap-frog update (Eq. leapfrog):
 //   v <- v + dt F ftm2v/m ; x' <- x + dt v ; flag a rebuild if |x' - x_ref| > skin/2.
 // Positions ping-pong between two buffers (neighbours read pos_in while the
 // new positions go to pos_out).
 template <int PREC, int LPA>
-__global__ __launch_bounds__(64 * LPA) void k_force_integrate(Geometry g, State s, Tables t,
-                                                              const double4* __restrict__ pos_in,
-                                                              double4* __restrict__ pos_out,
-                                                              int32_t* flag_next) {
+__global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
+    Geometry g, State s, Tables t, const double4* __restrict__ pos_in,
+    double4* __restrict__ pos_out, int32_t* flag_next) {
+  extern __shared__ double4 lds_d4[];
   if (has_error(s.status)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
-  const AtomTile tl = g.atiles[blockIdx.x];
-  const int a = threadIdx.x / LPA, sub = threadIdx.x % LPA;
-  const bool active = a < tl.count;
-  const RepDev& rp = g.reps[tl.rep];
-  const int64_t i = tl.begin + (active ? a : 0);
-  const double4 pi = pos_in[i];
-  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-  double fx, fy, fz;
-  pair_forces<PREC, LPA>(g, s, t, rp, pos_in, i, m, sub, pi, fx, fy, fz);
-  bool far = false;
-  if (active && sub == 0) {
-    double4 v = s.vel[i];
-    const double k = g.dt * g.acc;
-    v.x = fma(k, fx, v.x);
-    v.y = fma(k, fy, v.y);
-    v.z = fma(k, fz, v.z);
-    double4 xn;
-    xn.x = fma(g.dt, v.x, pi.x);
-    xn.y = fma(g.dt, v.y, pi.y);
-    xn.z = fma(g.dt, v.z, pi.z);
-    xn.w = 0.0;
-    pos_out[i] = xn;
-    s.vel[i] = v;
-    const double4 xr = s.xref[i];
-    const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
-    const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
-    far = !(d2 <= g.lim2);  // also true for NaN
-    if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z)) set_bits(s.status, ST_NONFINITE);
+  fill_force_table<PREC>(lds_d4, t);
+  __syncthreads();
+  const TileWalk w = tile_walk<LPA>();
+  for (int64_t it = w.q;; it += w.tpi) {
+    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
+    if (b >= g.n_atiles) break;
+    const AtomTile tl = g.atiles[b];
+    const bool active = w.a < tl.count;
+    const RepDev& rp = g.reps[tl.rep];
+    const int64_t i = tl.begin + (active ? w.a : 0);
+    const double4 pi = pos_in[i];
+    const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+    // own-atom state needed after the pair loop, fetched up front
+    double4 v = make_double4(0.0, 0.0, 0.0, 0.0), xr = v;
+    if (active && w.sub == 0) {
+      v = s.vel[i];
+      xr = s.xref[i];
+    }
+    double fx, fy, fz;
+    pair_forces<PREC, LPA>(g, s, t, rp, pos_in, lds_d4, i, m, w.sub, pi, fx, fy, fz);
+    bool far = false;
+    if (active && w.sub == 0) {
+      const double k = g.dt * g.acc;
+      v.x = fma(k, fx, v.x);
+      v.y = fma(k, fy, v.y);
+      v.z = fma(k, fz, v.z);
+      double4 xn;
+      xn.x = fma(g.dt, v.x, pi.x);
+      xn.y = fma(g.dt, v.y, pi.y);
+      xn.z = fma(g.dt, v.z, pi.z);
+      xn.w = 0.0;
+      pos_out[i] = xn;
+      s.vel[i] = v;
+      const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
+      const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
+      far = !(d2 <= g.lim2);  // also true for NaN
+      if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z))
+        set_bits(s.status, ST_NONFINITE);
+    }
+    if (__ballot(far) != 0ull && lane_id() == 0) *flag_next = 1;
   }
-  if (__ballot(far) != 0ull && lane_id() == 0) *flag_next = 1;
 }
 
 // Forces only (no integration), into s.frc.
 template <int PREC, int LPA>
-__global__ __launch_bounds__(64 * LPA) void k_force_only(Geometry g, State s, Tables t,
-                                                         const double4* __restrict__ pos) {
+__global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry g, State s,
+                                                                        Tables t,
+                                                                        const double4* __restrict__ pos) {
+  extern __shared__ double4 lds_d4[];
   if (has_error(s.status)) return;
-  const AtomTile tl = g.atiles[blockIdx.x];
-  const int a = threadIdx.x / LPA, sub = threadIdx.x % LPA;
-  const bool active = a < tl.count;
-  const RepDev& rp = g.reps[tl.rep];
-  const int64_t i = tl.begin + (active ? a : 0);
-  const double4 pi = pos[i];
-  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-  double fx, fy, fz;
-  pair_forces<PREC, LPA>(g, s, t, rp, pos, i, m, sub, pi, fx, fy, fz);
-  if (active && sub == 0) {
-    s.frc[i] = make_double4(fx, fy, fz, 0.0);
-    if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
+  fill_force_table<PREC>(lds_d4, t);
+  __syncthreads();
+  const TileWalk w = tile_walk<LPA>();
+  for (int64_t it = w.q;; it += w.tpi) {
+    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
+    if (b >= g.n_atiles) break;
+    const AtomTile tl = g.atiles[b];
+    const bool active = w.a < tl.count;
+    const RepDev& rp = g.reps[tl.rep];
+    const int64_t i = tl.begin + (active ? w.a : 0);
+    const double4 pi = pos[i];
+    const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+    double fx, fy, fz;
+    pair_forces<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, m, w.sub, pi, fx, fy, fz);
+    if (active && w.sub == 0) {
+      s.frc[i] = make_double4(fx, fy, fz, 0.0);
+      if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
+    }
   }
 }
 
@@ -811,6 +985,11 @@ hipError_t launch_import(const Launch& L, const Geometry& g, const State& s, con
   return hipGetLastError();
 }
 
+hipError_t launch_cell_stats(const Launch& L, const State& s, int64_t n_cells_total) {
+  hipLaunchKernelGGL(k_cell_stats, dim3(1), dim3(1024), 0, L.stream, s, n_cells_total);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_total) {
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_stride_blocks(n_cells_total)), dim3(256), 0, L.stream,
                      s.bin_cnt, n_cells_total);
@@ -842,99 +1021,111 @@ hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64
   return hipGetLastError();
 }
 
-template <int PREC>
-static hipError_t density_lpa(const Launch& L, const Geometry& g, const State& s, const Tables& t,
-                              int lpa, double4* pos, const int32_t* cz, int32_t* cf, int64_t m,
-                              int want) {
-  switch (lpa) {
-    case 1:
-      hipLaunchKernelGGL((k_density<PREC, 1>), dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, t,
-                         pos, cz, cf, m, want);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_density<PREC, 2>), dim3(L.atile_blocks), dim3(128), 0, L.stream, g, s,
-                         t, pos, cz, cf, m, want);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_density<PREC, 4>), dim3(L.atile_blocks), dim3(256), 0, L.stream, g, s,
-                         t, pos, cz, cf, m, want);
-      break;
-    default:
-      hipLaunchKernelGGL((k_density<PREC, 8>), dim3(L.atile_blocks), dim3(512), 0, L.stream, g, s,
-                         t, pos, cz, cf, m, want);
-      break;
-  }
+// Persistent launches: one workgroup per CU slot (grid = L.persist_blocks).
+static int pair_threads(int prec, bool force, int lpa) {
+  const int waves = (force && prec == 0) ? 12 : 16;
+  int tpi = waves / lpa;
+  if (tpi < 1) tpi = 1;
+  return 64 * lpa * tpi;
+}
+
+size_t density_lds_bytes(const Tables& t, int prec) {
+  return (size_t)(t.nr - 1) * (prec == 0 ? sizeof(double4) : sizeof(float4));
+}
+
+size_t force_lds_bytes(const Tables& t, int prec) {
+  return (size_t)(t.nr - 1) * (prec == 0 ? 3 * sizeof(double2) : sizeof(float4) + sizeof(float2));
+}
+
+template <int PREC, int LPA>
+static hipError_t density_go(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                             double4* pos, const int32_t* cz, int32_t* cf, int64_t m, int want) {
+  hipLaunchKernelGGL((k_density<PREC, LPA>), dim3(L.persist_blocks),
+                     dim3(pair_threads(PREC, false, LPA)), density_lds_bytes(t, PREC), L.stream, g,
+                     s, t, pos, cz, cf, m, want);
   return hipGetLastError();
 }
+
+template <int PREC, int LPA>
+static hipError_t force_int_go(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                               const double4* pi, double4* po, int32_t* fl) {
+  hipLaunchKernelGGL((k_force_integrate<PREC, LPA>), dim3(L.persist_blocks),
+                     dim3(pair_threads(PREC, true, LPA)), force_lds_bytes(t, PREC), L.stream, g, s,
+                     t, pi, po, fl);
+  return hipGetLastError();
+}
+
+template <int PREC, int LPA>
+static hipError_t force_only_go(const Launch& L, const Geometry& g, const State& s,
+                                const Tables& t, const double4* pos) {
+  hipLaunchKernelGGL((k_force_only<PREC, LPA>), dim3(L.persist_blocks),
+                     dim3(pair_threads(PREC, true, LPA)), force_lds_bytes(t, PREC), L.stream, g, s,
+                     t, pos);
+  return hipGetLastError();
+}
+
+#define MDK_LPA_SWITCH(P, lpa, CALL) \
+  switch (lpa) {                     \
+    case 1: return CALL(P, 1);       \
+    case 2: return CALL(P, 2);       \
+    case 4: return CALL(P, 4);       \
+    default: return CALL(P, 8);      \
+  }
 
 hipError_t launch_density(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                           int precision, int lpa, const double4* pos, const int32_t* cond_zero,
                           int32_t* clear_flag, int64_t n_cells_total, bool want_rho) {
   double4* p = const_cast<double4*>(pos);
-  if (precision == 0)
-    return density_lpa<0>(L, g, s, t, lpa, p, cond_zero, clear_flag, n_cells_total, want_rho);
-  return density_lpa<1>(L, g, s, t, lpa, p, cond_zero, clear_flag, n_cells_total, want_rho);
-}
-
-template <int PREC>
-static hipError_t force_int_lpa(const Launch& L, const Geometry& g, const State& s, const Tables& t,
-                                int lpa, const double4* pi, double4* po, int32_t* fl) {
-  switch (lpa) {
-    case 1:
-      hipLaunchKernelGGL((k_force_integrate<PREC, 1>), dim3(L.atile_blocks), dim3(64), 0, L.stream,
-                         g, s, t, pi, po, fl);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_force_integrate<PREC, 2>), dim3(L.atile_blocks), dim3(128), 0,
-                         L.stream, g, s, t, pi, po, fl);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_force_integrate<PREC, 4>), dim3(L.atile_blocks), dim3(256), 0,
-                         L.stream, g, s, t, pi, po, fl);
-      break;
-    default:
-      hipLaunchKernelGGL((k_force_integrate<PREC, 8>), dim3(L.atile_blocks), dim3(512), 0,
-                         L.stream, g, s, t, pi, po, fl);
-      break;
-  }
-  return hipGetLastError();
+  const int w = want_rho ? 1 : 0;
+#define MDK_D(P, Lp) density_go<P, Lp>(L, g, s, t, p, cond_zero, clear_flag, n_cells_total, w)
+  if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_D) }
+  MDK_LPA_SWITCH(1, lpa, MDK_D)
+#undef MDK_D
 }
 
 hipError_t launch_force_integrate(const Launch& L, const Geometry& g, const State& s,
                                   const Tables& t, int precision, int lpa, const double4* pos_in,
                                   double4* pos_out, int32_t* flag_next) {
-  if (precision == 0) return force_int_lpa<0>(L, g, s, t, lpa, pos_in, pos_out, flag_next);
-  return force_int_lpa<1>(L, g, s, t, lpa, pos_in, pos_out, flag_next);
-}
-
-template <int PREC>
-static hipError_t force_only_lpa(const Launch& L, const Geometry& g, const State& s,
-                                 const Tables& t, int lpa, const double4* pos) {
-  switch (lpa) {
-    case 1:
-      hipLaunchKernelGGL((k_force_only<PREC, 1>), dim3(L.atile_blocks), dim3(64), 0, L.stream, g,
-                         s, t, pos);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_force_only<PREC, 2>), dim3(L.atile_blocks), dim3(128), 0, L.stream, g,
-                         s, t, pos);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_force_only<PREC, 4>), dim3(L.atile_blocks), dim3(256), 0, L.stream, g,
-                         s, t, pos);
-      break;
-    default:
-      hipLaunchKernelGGL((k_force_only<PREC, 8>), dim3(L.atile_blocks), dim3(512), 0, L.stream, g,
-                         s, t, pos);
-      break;
-  }
-  return hipGetLastError();
+#define MDK_F(P, Lp) force_int_go<P, Lp>(L, g, s, t, pos_in, pos_out, flag_next)
+  if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_F) }
+  MDK_LPA_SWITCH(1, lpa, MDK_F)
+#undef MDK_F
 }
 
 hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                              int precision, int lpa, const double4* pos) {
-  if (precision == 0) return force_only_lpa<0>(L, g, s, t, lpa, pos);
-  return force_only_lpa<1>(L, g, s, t, lpa, pos);
+#define MDK_O(P, Lp) force_only_go<P, Lp>(L, g, s, t, pos)
+  if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_O) }
+  MDK_LPA_SWITCH(1, lpa, MDK_O)
+#undef MDK_O
+}
+
+// Dynamic LDS above the default limit must be allowed per kernel.
+template <int PREC, int LPA>
+static hipError_t allow_lds_one(size_t dens, size_t force) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_density<PREC, LPA>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)dens);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_integrate<PREC, LPA>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)force);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_force_only<PREC, LPA>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)force);
+}
+
+hipError_t allow_pair_lds(const Tables& t, int precision) {
+  const size_t d = density_lds_bytes(t, precision), f = force_lds_bytes(t, precision);
+  hipError_t e;
+  if (precision == 0) {
+    if ((e = allow_lds_one<0, 1>(d, f)) != hipSuccess) return e;
+    if ((e = allow_lds_one<0, 2>(d, f)) != hipSuccess) return e;
+    if ((e = allow_lds_one<0, 4>(d, f)) != hipSuccess) return e;
+    return allow_lds_one<0, 8>(d, f);
+  }
+  if ((e = allow_lds_one<1, 1>(d, f)) != hipSuccess) return e;
+  if ((e = allow_lds_one<1, 2>(d, f)) != hipSuccess) return e;
+  if ((e = allow_lds_one<1, 4>(d, f)) != hipSuccess) return e;
+  return allow_lds_one<1, 8>(d, f);
 }
 
 hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double scale) {

@@ -20,7 +20,7 @@ MD_E_ARG, MD_E_BOX, MD_E_TABLE, MD_E_NBR_OVERFLOW, MD_E_CELL_OVERFLOW = -1, -2, 
 MD_E_NONFINITE, MD_E_HIP, MD_E_ORDER, MD_E_LOST_ATOM, MD_E_WORKSPACE = -6, -7, -8, -9, -10
 MD_W_RHO_RANGE = 1
 MD_FP64, MD_MIXED = 0, 1
-PASS_DENSITY, PASS_FORCE, PASS_BUILD, PASS_BIN = 0, 1, 2, 3
+PASS_DENSITY, PASS_FORCE, PASS_BUILD, PASS_BIN, PASS_FORCE_RAW = 0, 1, 2, 3, 4
 
 
 class MDError(RuntimeError):
