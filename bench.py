@@ -163,6 +163,9 @@ def main() -> int:
     box = configs.config_128k()
     log(f"workload 128k: n={box.n} box={box.box[0]:.3f} A; building")
     s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100, lpa=args.lpa)
+    if args.lpa == 0:
+        lpa, us = s.autotune(10)
+        log(f"autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
     pe0, ke0 = s.energy()
     log(f"warmup {args.warmup} steps")
     s.step(args.warmup)
@@ -222,6 +225,9 @@ def main() -> int:
         for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
             log(f"secondary 810k {name}: n={big.n}")
             sb = make_system(md, big, tabs, precision=prec, chunk=100, lpa=args.lpa)
+            if args.lpa == 0:
+                lpa, us = sb.autotune(5)
+                log(f"  autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
             sb.step(100)
             t2, _ = time_steps(torch, sb, args.secondary_steps)
             stb = sb.stats()

@@ -171,6 +171,17 @@ md_status md_get_neighbors(md_ctx* ctx, int32_t* cnt, int32_t* nbr, int32_t cap_
  * so the state is not usable afterwards until md_set_state. */
 md_status md_launch_pass(md_ctx* ctx, int32_t pass, int32_t reps);
 
+/* Pair-pass schedule: lanes per atom (1, 2, 4 or 8) cooperating on one
+ * atom's neighbour list, with a fixed-order shuffle reduction.  Results are
+ * identical up to that reduction order.  Drops the captured step graph. */
+md_status md_set_schedule(md_ctx* ctx, int32_t lanes_per_atom);
+
+/* Autotuner: times reps rounds of the density and force passes at the
+ * current state for every lanes-per-atom choice (HIP events on the context
+ * stream), keeps the fastest and reports it (either pointer may be NULL).
+ * Leaves the state unchanged.  Requires md_build_neighbors. */
+md_status md_autotune(md_ctx* ctx, int32_t reps, int32_t* best_lanes_per_atom, float* best_us);
+
 /* Last error text of this context (or of the library when ctx is NULL). */
 const char* md_last_error(const md_ctx* ctx);
 const char* md_status_string(md_status s);

@@ -224,6 +224,8 @@ md_status gather_reps(const md_params* p, int32_t n_rep, const int64_t* rep_atom
     if (s != MD_OK) return s;
   }
   if (tot >= (int64_t(1) << kIndexBits)) return MD_E_ARG;
+  // the list is addressed with 32-bit byte offsets
+  if ((uint64_t)tot * (uint64_t)p->nbr_capacity * 4ull >= (1ull << 32)) return MD_E_ARG;
   return MD_OK;
 }
 
@@ -784,6 +786,67 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
       break;
   }
   return MD_OK;
+}
+
+md_status md_set_schedule(md_ctx* c, int32_t lanes_per_atom) {
+  if (!c) return MD_E_ARG;
+  const int l = lanes_per_atom;
+  if (!(l == 1 || l == 2 || l == 4 || l == 8)) return MD_E_ARG;
+  if (l != c->lpa && c->graph) {
+    HIPC(c, hipStreamSynchronize(c->L.stream));
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  c->lpa = l;
+  return MD_OK;
+}
+
+md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us) {
+  if (!c || reps < 1) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  State& s = c->st[c->cur];
+  hipEvent_t e0, e1;
+  HIPC(c, hipEventCreate(&e0));
+  HIPC(c, hipEventCreate(&e1));
+  const int cand[4] = {1, 2, 4, 8};
+  float best = 3.4e38f;
+  int pick = c->lpa;
+  md_status rc = MD_OK;
+  for (int q = 0; q < 4 && rc == MD_OK; ++q) {
+    const int l = cand[q];
+    // one untimed round, then reps timed rounds of density + forces (the
+    // same pair code the step uses; forces go to the scratch force buffer)
+    for (int r = 0; r <= reps && rc == MD_OK; ++r) {
+      if (r == 1) {
+        hipError_t e = hipEventRecord(e0, c->L.stream);
+        if (e != hipSuccess) rc = hip_fail(c, e, "hipEventRecord");
+      }
+      hipError_t e = launch_density(c->L, c->g, s, c->t, c->p.precision, l, s.pos, nullptr,
+                                    nullptr, c->sz.cells, false);
+      if (e == hipSuccess) e = launch_force_only(c->L, c->g, s, c->t, c->p.precision, l, s.pos);
+      if (e != hipSuccess) rc = hip_fail(c, e, "autotune launch");
+    }
+    if (rc != MD_OK) break;
+    float ms = 0.f;
+    hipError_t e = hipEventRecord(e1, c->L.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = hip_fail(c, e, "autotune timing");
+      break;
+    }
+    const float us = 1000.f * ms / (float)reps;
+    if (us < best) {
+      best = us;
+      pick = l;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != MD_OK) return rc;
+  if (best_lpa) *best_lpa = pick;
+  if (best_us) *best_us = best;
+  return md_set_schedule(c, pick);
 }
 
 void md_destroy(md_ctx* c) {

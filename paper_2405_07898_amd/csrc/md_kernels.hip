@@ -30,16 +30,14 @@ __device__ __forceinline__ double wrap1(double x, double L) {
   return x;
 }
 
-// 1/sqrt(x) in float64: hardware estimate, then two Newton-Raphson steps
-// y <- y + y/2 (1 - x y^2) (the paper evaluates r^-1 = (r^2)^-1/2 by
-// Newton-Raphson, Table "flopmodel").
+// 1/sqrt(x) in float64: hardware estimate (relative error below 2^-24 on
+// gfx950, measured), then one Newton-Raphson step y <- y + y/2 (1 - x y^2),
+// which leaves a relative error of a few 1e-15 (the paper evaluates
+// r^-1 = (r^2)^-1/2 by Newton-Raphson, Table "flopmodel").
 __device__ __forceinline__ double rsq64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double h = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, h, y);
-  h = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, h, y);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, h, y);
 }
 
 // Knuth TwoSum accumulation of v into (s, c): s + c carries the exact sum of
@@ -85,6 +83,19 @@ __device__ __forceinline__ void apply_shift(uint32_t code, const RepDev& rp, dou
   dx += (double)((int)(code & 3u) - 1) * rp.box[0];
   dy += (double)((int)((code >> 2) & 3u) - 1) * rp.box[1];
   dz += (double)((int)(code >> 4) - 1) * rp.box[2];
+}
+
+// Loads through a uniform base pointer and a 32-bit byte offset (the
+// compiler's scalar-base + 32-bit vector-offset addressing; every buffer that
+// is indexed this way is below 4 GiB, checked when the context is created).
+template <class T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+template <class T>
+__device__ __forceinline__ void st32(T* __restrict__ base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
 // ============================================================ import / export
@@ -203,9 +214,29 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
   }
   const int32_t cl = (c[2] * rp.nc[1] + c[1]) * rp.nc[0] + c[0];
   s.cell_of[i] = cl;
-  const int64_t cg = (int64_t)rp.cell0 + cl;
-  const int32_t slot = atomicAdd(&s.bin_cnt[cg], 1);
-  if (slot < g.cell_cap) s.bin_idx[cg * g.cell_cap + slot] = (int32_t)i;
+  const int32_t cg = rp.cell0 + cl;
+  // Atoms of a wave are mostly in a few cells (cell-sorted order): group the
+  // lanes by cell, let one leader per cell reserve all their slots with one
+  // atomic, and rank the others behind it.
+  const int lane = lane_id();
+  unsigned long long todo = __ballot(1);
+  int leader = lane, rank = 0, count = 0;
+  while (todo) {
+    const int l = __builtin_ctzll(todo);
+    const int32_t c0 = __shfl(cg, l, 64);
+    const unsigned long long peers = __ballot(cg == c0) & todo;
+    if (cg == c0) {
+      leader = l;
+      rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+    }
+    if (lane == l) count = __popcll(peers);
+    todo &= ~peers;
+  }
+  int base = 0;
+  if (lane == leader) base = atomicAdd(&s.bin_cnt[cg], count);
+  const int32_t slot = __shfl(base, leader, 64) + rank;
+  if (slot < g.cell_cap) s.bin_idx[(int64_t)cg * g.cell_cap + slot] = (int32_t)i;
   else set_bits(s.status, ST_CELL_OVERFLOW);
 }
 
@@ -313,7 +344,8 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
 #pragma unroll
     for (int k = 0; k < kBuildChunks; ++k) {
       const int p = k * 64 + lane;
-      px[k] = py[k] = pz[k] = 0.0;
+      // empty slots sit infinitely far away: r^2 = inf fails the test
+      px[k] = py[k] = pz[k] = HUGE_VAL;
       sx[k] = sy[k] = sz[k] = 0.0;
       ent[k] = 0xffffffffu;
       if (p < T) {
@@ -331,6 +363,7 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
     }
     for (int u = 0; u < n_c; ++u) {
       const int32_t i = s_center[u];
+      const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
       const double qx = s_cx[u], qy = s_cy[u], qz = s_cz[u];
       int base = s_base[u];
 #pragma unroll
@@ -340,12 +373,14 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
         const double dy = fma(sy[k], Ly, py[k] - qy);
         const double dz = fma(sz[k], Lz, pz[k] - qz);
         const double r2 = (dx * dx + dy * dy) + dz * dz;
-        const bool ok = ent[k] != 0xffffffffu && (int32_t)(ent[k] & kIndexMask) != i && r2 < rl2;
+        // the centre atom itself is the only candidate with its own id in the
+        // centre cell (code kNoShift)
+        const bool ok = ent[k] != self_e && r2 < rl2;
         const unsigned long long m = __ballot(ok);
         if (ok) {
-          const int kk = base + (int)__builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (kk < cap) s.nbr[(int64_t)kk * N + i] = ent[k];
+          const uint32_t kk = (uint32_t)base + __builtin_amdgcn_mbcnt_hi(
+                                   (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (kk < (uint32_t)cap) st32(s.nbr, (kk * (uint32_t)N + (uint32_t)i) * 4u, ent[k]);
         }
         base += __popcll(m);
       }
@@ -531,18 +566,6 @@ __device__ __forceinline__ void lds_fill(T* dst, const T* __restrict__ src, int 
   for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
 }
 
-template <int LPA>
-__device__ __forceinline__ void load_entries(const uint32_t* __restrict__ lst, int64_t N, int k0,
-                                             int m, uint32_t self_e, uint32_t (&e)[kBatch],
-                                             bool (&v)[kBatch]) {
-#pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
-    const int k = k0 + u * LPA;
-    v[u] = k < m;
-    e[u] = v[u] ? lst[(int64_t)k * N] : self_e;
-  }
-}
-
 __device__ __forceinline__ void separation(uint32_t e, const RepDev& rp, double qx, double qy,
                                            double qz, double px, double py, double pz, double& dx,
                                            double& dy, double& dz) {
@@ -553,55 +576,67 @@ __device__ __forceinline__ void separation(uint32_t e, const RepDev& rp, double 
   if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
 }
 
-// rho_i of one atom (its lane's share), table rows from LDS.
+// rho_i of one atom (its lane's share), table rows from LDS.  Each batch
+// loads kBatch list entries, then their positions, then table rows.
+template <int LPA>
+__device__ __forceinline__ void load_entries(const uint32_t* __restrict__ nbr, uint32_t N,
+                                             uint32_t i, int k0, int m, uint32_t self_e,
+                                             uint32_t (&e)[kBatch]) {
+  uint32_t off = ((uint32_t)k0 * N + i) * 4u;
+  const uint32_t step = (uint32_t)LPA * N * 4u;
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    e[u] = (k0 + u * LPA < m) ? ld32(nbr, off) : self_e;
+    off += step;
+  }
+}
+
 template <int PREC, int LPA>
 __device__ __forceinline__ double density_of(const Geometry& g, const State& s, const Tables& t,
                                              const RepDev& rp, const double4* __restrict__ pos,
-                                             const void* lds_tab, int64_t i, int m, int sub) {
-  const int64_t N = g.n;
+                                             const void* lds_tab, int64_t i, bool active,
+                                             int sub) {
+  const uint32_t N = (uint32_t)g.n;
+  const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
+  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
   const double2 pxy = *reinterpret_cast<const double2*>(&pos[i]);
   const double pz = pos[i].z;
-  const uint32_t* __restrict__ lst = s.nbr + i;
-  const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
   const int last = t.nr - 2;
   double acc = 0.0;
   float sum = 0.0f, comp = 0.0f;
+  const double2* __restrict__ pos2 = reinterpret_cast<const double2*>(pos);
+  const double* __restrict__ posd = reinterpret_cast<const double*>(pos);
   for (int k0 = sub; k0 < m; k0 += LPA * kBatch) {
     uint32_t e[kBatch];
-    bool v[kBatch];
-    load_entries<LPA>(lst, N, k0, m, self_e, e, v);
+    load_entries<LPA>(s.nbr, N, (uint32_t)i, k0, m, self_e, e);
     double2 qxy[kBatch];
     double qz[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const uint32_t j = e[u] & kIndexMask;
-      qxy[u] = *reinterpret_cast<const double2*>(&pos[j]);
-      qz[u] = pos[j].z;
+      const uint32_t off = (e[u] & kIndexMask) * 32u;
+      qxy[u] = ld32(pos2, off);
+      qz[u] = ld32(posd, off + 16u);
     }
-    if (PREC == 0) {
-      const double4* tab = reinterpret_cast<const double4*>(lds_tab);
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        double dx, dy, dz;
-        separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
+    for (int u = 0; u < kBatch; ++u) {
+      const bool v = k0 + u * LPA < m;
+      double dx, dy, dz;
+      separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
+      if (PREC == 0) {
+        const double4* tab = reinterpret_cast<const double4*>(lds_tab);
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const bool in = v[u] && r2 < g.rc2;
+        const bool in = v && r2 < g.rc2;
         const double rr = in ? r2 : 1.0;
         const double x = (rr * rsq64(rr)) * t.r_inv_dx;
         const int kk = min(max((int)x, 0), last);
         const double tt = x - (double)kk;
         const double4 c = tab[kk];
         if (in) acc += fma(fma(fma(c.w, tt, c.z), tt, c.y), tt, c.x);
-      }
-    } else {
-      const float4* tab = reinterpret_cast<const float4*>(lds_tab);
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        double dx, dy, dz;
-        separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
+      } else {
+        const float4* tab = reinterpret_cast<const float4*>(lds_tab);
         const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
         const float r2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
-        const bool in = v[u] && r2 < g.rc2f;
+        const bool in = v && r2 < g.rc2f;
         const float rr = in ? r2 : 1.0f;
         const float x = (rr * __builtin_amdgcn_rsqf(rr)) * t.r_inv_dx32;
         const int kk = min(max((int)x, 0), last);
@@ -620,7 +655,7 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
 // Side jobs used inside the step graph: clear the next step's rebuild flag,
 // and zero the bins after a rebuild (cond_zero set).
 template <int PREC, int LPA>
-__global__ __launch_bounds__(1024) void k_density(Geometry g, State s, Tables t,
+__global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
                                                   double4* __restrict__ pos,
                                                   const int32_t* cond_zero, int32_t* clear_flag,
                                                   int64_t ncells, int want_rho) {
@@ -643,8 +678,7 @@ __global__ __launch_bounds__(1024) void k_density(Geometry g, State s, Tables t,
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];
     const int64_t i = tl.begin + (active ? w.a : 0);
-    const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-    const double rho_i = density_of<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, m, w.sub);
+    const double rho_i = density_of<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, active, w.sub);
     if (!active || w.sub != 0) continue;
     // F'(rho_i) from the embedding table (float64 for both forms)
     const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
@@ -664,34 +698,34 @@ __global__ __launch_bounds__(1024) void k_density(Geometry g, State s, Tables t,
 
 // F_i = sum_j [(F'_i + F'_j) rho'(r) + phi'(r)] (x_j - x_i)/r   (Eq. EAMforce),
 // derivative rows from LDS (float64: 3 double2 per segment; mixed: float4 +
-// float2 arrays).
+// float2 arrays).  Same batching as the density pass.
 template <int PREC, int LPA>
 __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, const Tables& t,
                                             const RepDev& rp, const double4* __restrict__ pos,
-                                            const void* lds_tab, int64_t i, int m, int sub,
+                                            const void* lds_tab, int64_t i, bool active, int sub,
                                             double4 pi, double& fx, double& fy, double& fz) {
-  const uint32_t* __restrict__ lst = s.nbr + i;
-  const int64_t N = g.n;
-  const int last = t.nr - 2;
+  const uint32_t N = (uint32_t)g.n;
   const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
+  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+  const int last = t.nr - 2;
   double ax = 0.0, ay = 0.0, az = 0.0;
   float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
   const float fpi = (float)pi.w;
   for (int k0 = sub; k0 < m; k0 += LPA * kBatch) {
     uint32_t e[kBatch];
-    bool v[kBatch];
-    load_entries<LPA>(lst, N, k0, m, self_e, e, v);
+    load_entries<LPA>(s.nbr, N, (uint32_t)i, k0, m, self_e, e);
     double4 q[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) q[u] = pos[e[u] & kIndexMask];
-    if (PREC == 0) {
-      const double2* tab = reinterpret_cast<const double2*>(lds_tab);
+    for (int u = 0; u < kBatch; ++u) q[u] = ld32(pos, (e[u] & kIndexMask) * 32u);
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        double dx, dy, dz;
-        separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
+    for (int u = 0; u < kBatch; ++u) {
+      const bool v = k0 + u * LPA < m;
+      double dx, dy, dz;
+      separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
+      if (PREC == 0) {
+        const double2* tab = reinterpret_cast<const double2*>(lds_tab);
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const bool in = v[u] && r2 < g.rc2;
+        const bool in = v && r2 < g.rc2;
         const double rr = in ? r2 : 1.0;
         const double rinv = rsq64(rr);
         const double x = (rr * rinv) * t.r_inv_dx;
@@ -707,17 +741,12 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
           ay = fma(sc, dy, ay);
           az = fma(sc, dz, az);
         }
-      }
-    } else {
-      const float4* ta = reinterpret_cast<const float4*>(lds_tab);
-      const float2* tb = reinterpret_cast<const float2*>(ta + (t.nr - 1));
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        double dx, dy, dz;
-        separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
+      } else {
+        const float4* ta = reinterpret_cast<const float4*>(lds_tab);
+        const float2* tb = reinterpret_cast<const float2*>(ta + (t.nr - 1));
         const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
         const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-        const bool in = v[u] && r2 < g.rc2f;
+        const bool in = v && r2 < g.rc2f;
         const float rr = in ? r2 : 1.0f;
         const float rinv = __builtin_amdgcn_rsqf(rr);
         const float x = (rr * rinv) * t.r_inv_dx32;
@@ -783,7 +812,6 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
     const RepDev& rp = g.reps[tl.rep];
     const int64_t i = tl.begin + (active ? w.a : 0);
     const double4 pi = pos_in[i];
-    const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
     // own-atom state needed after the pair loop, fetched up front
     double4 v = make_double4(0.0, 0.0, 0.0, 0.0), xr = v;
     if (active && w.sub == 0) {
@@ -791,7 +819,7 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
       xr = s.xref[i];
     }
     double fx, fy, fz;
-    pair_forces<PREC, LPA>(g, s, t, rp, pos_in, lds_d4, i, m, w.sub, pi, fx, fy, fz);
+    pair_forces<PREC, LPA>(g, s, t, rp, pos_in, lds_d4, i, active, w.sub, pi, fx, fy, fz);
     bool far = false;
     if (active && w.sub == 0) {
       const double k = g.dt * g.acc;
@@ -833,9 +861,8 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry 
     const RepDev& rp = g.reps[tl.rep];
     const int64_t i = tl.begin + (active ? w.a : 0);
     const double4 pi = pos[i];
-    const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
     double fx, fy, fz;
-    pair_forces<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, m, w.sub, pi, fx, fy, fz);
+    pair_forces<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, active, w.sub, pi, fx, fy, fz);
     if (active && w.sub == 0) {
       s.frc[i] = make_double4(fx, fy, fz, 0.0);
       if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
@@ -1023,7 +1050,7 @@ hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64
 
 // Persistent launches: one workgroup per CU slot (grid = L.persist_blocks).
 static int pair_threads(int prec, bool force, int lpa) {
-  const int waves = (force && prec == 0) ? 12 : 16;
+  const int waves = (force && prec != 0) ? 16 : 12;
   int tpi = waves / lpa;
   if (tpi < 1) tpi = 1;
   return 64 * lpa * tpi;
@@ -1040,7 +1067,7 @@ size_t force_lds_bytes(const Tables& t, int prec) {
 template <int PREC, int LPA>
 static hipError_t density_go(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                              double4* pos, const int32_t* cz, int32_t* cf, int64_t m, int want) {
-  hipLaunchKernelGGL((k_density<PREC, LPA>), dim3(L.persist_blocks),
+  hipLaunchKernelGGL((k_density<PREC, LPA>), dim3(2 * L.persist_blocks),
                      dim3(pair_threads(PREC, false, LPA)), density_lds_bytes(t, PREC), L.stream, g,
                      s, t, pos, cz, cf, m, want);
   return hipGetLastError();

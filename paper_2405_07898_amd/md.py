@@ -53,7 +53,8 @@ _lib = None
 EXPORTED = [
     "md_workspace_size", "md_create", "md_set_state", "md_build_neighbors", "md_step",
     "md_energy", "md_get_state", "md_compute_forces", "md_stats", "md_get_cells",
-    "md_get_neighbors", "md_launch_pass", "md_last_error", "md_status_string", "md_destroy",
+    "md_get_neighbors", "md_launch_pass", "md_set_schedule", "md_autotune", "md_last_error",
+    "md_status_string", "md_destroy",
     "md_fm_workspace_size", "md_fm_create", "md_fm_forward", "md_fm_backward", "md_fm_destroy",
 ]
 
@@ -81,6 +82,8 @@ def lib():
             "md_get_cells": (i32, [vp, vp]),
             "md_get_neighbors": (i32, [vp, vp, vp, i32]),
             "md_launch_pass": (i32, [vp, i32, i32]),
+            "md_set_schedule": (i32, [vp, i32]),
+            "md_autotune": (i32, [vp, i32, P(i32), P(C.c_float)]),
             "md_last_error": (C.c_char_p, [vp]),
             "md_status_string": (C.c_char_p, [i32]),
             "md_destroy": (None, [vp]),
@@ -253,6 +256,17 @@ class System:
     def launch_pass(self, which: int, reps: int):
         return _check(lib().md_launch_pass(self.ctx, int(which), int(reps)), "md_launch_pass",
                       self.ctx)
+
+    def set_schedule(self, lanes_per_atom: int):
+        return _check(lib().md_set_schedule(self.ctx, int(lanes_per_atom)), "md_set_schedule",
+                      self.ctx)
+
+    def autotune(self, reps: int = 20):
+        lpa = C.c_int32()
+        us = C.c_float()
+        _check(lib().md_autotune(self.ctx, int(reps), C.byref(lpa), C.byref(us)), "md_autotune",
+               self.ctx)
+        return int(lpa.value), float(us.value)
 
     def close(self):
         if getattr(self, "ctx", None):
