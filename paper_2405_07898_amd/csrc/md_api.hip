@@ -349,6 +349,16 @@ void build_tables(const md_spline* phi, const md_spline* rho, const md_spline* e
 
 }  // namespace
 
+int md_internal_view(const md_ctx* c, mdk::CtxView* out) {
+  if (!c || !out || !c->built) return MD_E_ORDER;
+  out->g = c->g;
+  out->s = c->st[c->cur];
+  out->L = c->L;
+  out->n_cells = c->sz.cells;
+  out->n_rep = c->n_rep;
+  return MD_OK;
+}
+
 extern "C" {
 
 const char* md_status_string(md_status s) {

@@ -164,4 +164,18 @@ hipError_t launch_export_nbrs(const Launch& L, const Geometry& g, const State& s
 hipError_t launch_snapshot(const Launch& L, const Geometry& g, const State& s, double4* snap_pos,
                            double4* snap_vel, bool restore);
 
+// Read-only view of a context's device state for companion modules (force
+// matching): geometry, the current-buffer state and launch configuration.
+struct CtxView {
+  Geometry g;
+  State s;
+  Launch L;
+  int64_t n_cells;
+  int32_t n_rep;
+};
+
 }  // namespace mdk
+
+struct md_ctx;
+// Defined in md_api.hip; valid after md_build_neighbors.
+int md_internal_view(const md_ctx* ctx, mdk::CtxView* out);

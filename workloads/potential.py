@@ -145,7 +145,7 @@ def spline_value_map(n_knots: int) -> np.ndarray:
 # --- force-matching model (perturbed coarse splines) --------------------------
 
 FM_KNOTS = 64
-FM_RHO_MAX = 8.0
+FM_RHO_MAX = 16.0  # covers rho_i of the hottest snapshots (about 11.3)
 FM_NOISE = 0.05
 
 
@@ -153,7 +153,7 @@ def fm_knot_values(seed: int = 55):
     """Knot values of the perturbed 64-knot phi, rho, F splines.
 
     Each analytic function is sampled at 64 equally spaced knots (phi, rho on
-    [0, rc]; F on [0, 8]) and every knot value is scaled by (1 + 0.05 xi) with
+    [0, rc]; F on [0, 16]) and every knot value is scaled by (1 + 0.05 xi) with
     xi ~ N(0, 1) drawn from default_rng(seed) in the order phi, rho, F.
     Returns ((x1, y) for phi, rho, F).
     """
