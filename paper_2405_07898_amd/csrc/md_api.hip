@@ -159,7 +159,7 @@ struct Buffers {
   double *rho, *epair;
   int32_t *id, *cell_of, *cnt;
   uint32_t* nbr;
-  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *status;
+  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *status, *rflag;
   double4 *sort_pos, *sort_vel;
   int32_t* sort_id;
   double4 *snap_pos, *snap_vel;
@@ -199,6 +199,7 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.cell_start = c.take<int32_t>((size_t)s.cells + 1);
   o.cell_stat = c.take<int32_t>(3 * (size_t)s.cells);
   o.status = c.take<int32_t>(SW_WORDS);
+  o.rflag = c.take<int32_t>(3 * (size_t)n_rep);
   o.sort_pos = c.take<double4>(N);
   o.sort_vel = c.take<double4>(N);
   o.sort_id = c.take<int32_t>(N);
@@ -256,10 +257,11 @@ md_status status_code(int32_t bits) {
 md_status rebuild_sorted(md_ctx* c, bool sort) {
   State& s = c->st[c->cur];
   HIPC(c, hipMemsetAsync(c->status + SW_FLAG0, 0, 2 * sizeof(int32_t), c->L.stream));
+  HIPC(c, hipMemsetAsync(s.rflag, 0, 2 * (size_t)c->n_rep * sizeof(int32_t), c->L.stream));
   if (sort) HIPC(c, launch_sort(c->L, c->g, s, c->sz.cells));
   HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
-  HIPC(c, launch_bin(c->L, c->g, s, nullptr));
-  HIPC(c, launch_build(c->L, c->g, s, nullptr));
+  HIPC(c, launch_bin(c->L, c->g, s, nullptr, nullptr));
+  HIPC(c, launch_build(c->L, c->g, s, nullptr, nullptr));
   HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
   return MD_OK;
 }
@@ -267,7 +269,7 @@ md_status rebuild_sorted(md_ctx* c, bool sort) {
 md_status forces_now(md_ctx* c, bool want_rho) {
   State& s = c->st[c->cur];
   HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, nullptr, nullptr,
-                         c->sz.cells, want_rho));
+                         nullptr, c->sz.cells, want_rho));
   HIPC(c, launch_force_only(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos));
   return MD_OK;
 }
@@ -278,12 +280,14 @@ md_status step_eager(md_ctx* c) {
   State& s = c->st[k];
   int32_t* fl_cur = c->status + (k == 0 ? SW_FLAG0 : SW_FLAG1);
   int32_t* fl_nxt = c->status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
-  HIPC(c, launch_bin(c->L, c->g, s, fl_cur));
-  HIPC(c, launch_build(c->L, c->g, s, fl_cur));
+  int32_t* rf_cur = s.rflag + (k == 0 ? 0 : c->n_rep);
+  int32_t* rf_nxt = s.rflag + (k == 0 ? c->n_rep : 0);
+  HIPC(c, launch_bin(c->L, c->g, s, fl_cur, rf_cur));
+  HIPC(c, launch_build(c->L, c->g, s, fl_cur, rf_cur));
   HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, fl_cur, fl_nxt,
-                         c->sz.cells, false));
+                         rf_nxt, c->sz.cells, false));
   HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
-                                 c->st[1 - k].pos, fl_nxt));
+                                 c->st[1 - k].pos, fl_nxt, rf_nxt));
   c->cur = 1 - k;
   return MD_OK;
 }
@@ -450,6 +454,8 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
     d.n_atoms = (int32_t)reps[r].n;
     d.cell0 = (int32_t)c0;
     d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
+    d.tile0 = (int32_t)at.size();
+    d.ntiles = (int32_t)((reps[r].n + 63) / 64);
     for (int64_t t0 = 0; t0 < reps[r].n; t0 += 64)
       at.push_back(AtomTile{r, (int32_t)(a0 + t0), (int32_t)std::min<int64_t>(64, reps[r].n - t0), 0});
     for (int32_t q = 0; q < d.ncell; ++q) ct.push_back(CellTile{r, q});
@@ -488,6 +494,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   hipError_t e = hipMemset(b.status, 0, SW_WORDS * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.bin_cnt, 0, (size_t)ls.cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.cnt, 0, (size_t)ls.n * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(b.rflag, 0, 3 * (size_t)n_rep * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.cell_stat, 0, 3 * (size_t)ls.cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.frc, 0, (size_t)ls.n * sizeof(double4));
   if (e != hipSuccess) {
@@ -503,6 +510,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   g.n = ls.n;
   g.n_atiles = (int32_t)ls.atile_blocks;
   g.n_ctiles = (int32_t)ls.ctile_blocks;
+  g.n_rep = n_rep;
   g.nbr_cap = p->nbr_capacity;
   g.cell_cap = p->cell_capacity;
   g.rc2 = p->r_cut * p->r_cut;
@@ -568,6 +576,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   base.cell_start = b.cell_start;
   base.cell_stat = b.cell_stat;
   base.status = b.status;
+  base.rflag = b.rflag;
   base.sort_pos = b.sort_pos;
   base.sort_vel = b.sort_vel;
   base.sort_id = b.sort_id;
@@ -760,7 +769,7 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
     case 0:
       for (int r = 0; r < reps; ++r)
         HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, nullptr,
-                               nullptr, c->sz.cells, false));
+                               nullptr, nullptr, c->sz.cells, false));
       break;
     case 1:
       // the kernel md_step runs, writing the other position buffer; positions,
@@ -768,7 +777,8 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
       HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, false));
       for (int r = 0; r < reps; ++r)
         HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
-                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH));
+                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
+                                       s.rflag + 2 * c->n_rep));
       HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, true));
       break;
     case 4:
@@ -776,22 +786,23 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
       // launch while positions are read from the unchanged current buffer
       for (int r = 0; r < reps; ++r)
         HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
-                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH));
+                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
+                                       s.rflag + 2 * c->n_rep));
       break;
     case 2:
       // list build from freshly filled bins (one binning first, bins zeroed after)
       HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
-      HIPC(c, launch_bin(c->L, c->g, s, nullptr));
-      for (int r = 0; r < reps; ++r) HIPC(c, launch_build(c->L, c->g, s, nullptr));
+      HIPC(c, launch_bin(c->L, c->g, s, nullptr, nullptr));
+      for (int r = 0; r < reps; ++r) HIPC(c, launch_build(c->L, c->g, s, nullptr, nullptr));
       HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
       break;
     default:
       // binning (wraps positions and resets x_ref), then one build keeps the list consistent
       for (int r = 0; r < reps; ++r) {
         HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
-        HIPC(c, launch_bin(c->L, c->g, s, nullptr));
+        HIPC(c, launch_bin(c->L, c->g, s, nullptr, nullptr));
       }
-      HIPC(c, launch_build(c->L, c->g, s, nullptr));
+      HIPC(c, launch_build(c->L, c->g, s, nullptr, nullptr));
       HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
       break;
   }
@@ -832,7 +843,7 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
         if (e != hipSuccess) rc = hip_fail(c, e, "hipEventRecord");
       }
       hipError_t e = launch_density(c->L, c->g, s, c->t, c->p.precision, l, s.pos, nullptr,
-                                    nullptr, c->sz.cells, false);
+                                    nullptr, nullptr, c->sz.cells, false);
       if (e == hipSuccess) e = launch_force_only(c->L, c->g, s, c->t, c->p.precision, l, s.pos);
       if (e != hipSuccess) rc = hip_fail(c, e, "autotune launch");
     }

@@ -53,7 +53,9 @@ struct RepDev {
   int32_t cell0;
   int32_t nc[3];
   int32_t ncell;
-  int32_t pad[4];
+  int32_t tile0;   // first atom tile of the replica, in replica order
+  int32_t ntiles;  // atom tiles of the replica
+  int32_t pad[2];
 };
 
 struct AtomTile {
@@ -92,6 +94,7 @@ struct Geometry {
   int64_t n;        // total atoms (ELL stride)
   int32_t n_atiles;
   int32_t n_ctiles;
+  int32_t n_rep;
   int32_t nbr_cap;
   int32_t cell_cap;
   double rc2;       // r_cut^2
@@ -120,6 +123,7 @@ struct State {
   int32_t* cell_start;  // [total cells + 1]
   int32_t* cell_stat;   // [total cells][3]: longest list, list entries, atoms (last build)
   int32_t* status;   // SW_WORDS
+  int32_t* rflag;    // [3][n_rep]: per-replica rebuild requests (parity 0, 1, scratch)
   double4* sort_pos;
   double4* sort_vel;
   int32_t* sort_id;
@@ -139,15 +143,18 @@ hipError_t launch_import(const Launch& L, const Geometry& g, const State& s, con
                          const double* v);
 hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_total);
 hipError_t launch_cell_stats(const Launch& L, const State& s, int64_t n_cells_total);
-hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond);
-hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond);
+hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
+                      const int32_t* rcond);
+hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
+                        const int32_t* rcond);
 hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64_t n_cells_total);
 hipError_t launch_density(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                           int precision, int lpa, const double4* pos, const int32_t* cond_zero,
-                          int32_t* clear_flag, int64_t n_cells_total, bool want_rho);
+                          int32_t* clear_flag, int32_t* rclear, int64_t n_cells_total,
+                          bool want_rho);
 hipError_t launch_force_integrate(const Launch& L, const Geometry& g, const State& s,
                                   const Tables& t, int precision, int lpa, const double4* pos_in,
-                                  double4* pos_out, int32_t* flag_next);
+                                  double4* pos_out, int32_t* flag_next, int32_t* rflag_next);
 hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                              int precision, int lpa, const double4* pos);
 size_t density_lds_bytes(const Tables& t, int precision);

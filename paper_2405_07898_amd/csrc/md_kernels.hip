@@ -185,12 +185,14 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ p, int64
 // becomes 0), assign it to cell (cz*ny + cy)*nx + cx with
 // c_d = min(int(x_d * n_d/L_d), n_d - 1), append it to that cell's bin, and
 // snapshot the reference positions for the skin check.
-__global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* cond) {
+__global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* cond,
+                                            const int32_t* rcond) {
   if (cond && *cond == 0) return;
   if (has_error(s.status)) return;
   if (cond && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
   const AtomTile tl = g.atiles[blockIdx.x];
   if ((int)threadIdx.x >= tl.count) return;
+  if (rcond && rcond[tl.rep] == 0) return;  // this replica keeps its list
   const RepDev& rp = g.reps[tl.rep];
   const int64_t i = tl.begin + threadIdx.x;
   double4 p = s.pos[i];
@@ -257,11 +259,13 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
 // list radius under either rule.
 constexpr int kBuildChunks = kMaxStage / 64;
 
-__global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t* cond) {
+__global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t* cond,
+                                              const int32_t* rcond) {
   if (cond && *cond == 0) return;
   if (has_error(s.status)) return;
   const CellTile ct = g.ctiles[blockIdx.x];
   if (ct.cell < 0) return;
+  if (rcond && rcond[ct.rep] == 0) return;  // this replica keeps its list
   const RepDev& rp = g.reps[ct.rep];
   __shared__ int32_t s_q[27], s_n[27], s_off[28], s_code[27];
   __shared__ int32_t s_raw[kMaxStage];
@@ -658,9 +662,12 @@ template <int PREC, int LPA>
 __global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
                                                   double4* __restrict__ pos,
                                                   const int32_t* cond_zero, int32_t* clear_flag,
-                                                  int64_t ncells, int want_rho) {
+                                                  int32_t* rclear, int64_t ncells, int want_rho) {
   extern __shared__ double4 lds_d4[];
-  if (clear_flag && blockIdx.x == 0 && threadIdx.x == 0) *clear_flag = 0;
+  if (clear_flag && blockIdx.x == 0) {
+    if (threadIdx.x == 0) *clear_flag = 0;
+    for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rclear[r] = 0;
+  }
   if (cond_zero && *cond_zero) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncells;
          k += (int64_t)gridDim.x * blockDim.x)
@@ -797,7 +804,7 @@ __device__ __forceinline__ void fill_force_table(void* lds, const Tables& t) {
 template <int PREC, int LPA>
 __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
     Geometry g, State s, Tables t, const double4* __restrict__ pos_in,
-    double4* __restrict__ pos_out, int32_t* flag_next) {
+    double4* __restrict__ pos_out, int32_t* flag_next, int32_t* rflag_next) {
   extern __shared__ double4 lds_d4[];
   if (has_error(s.status)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
@@ -839,7 +846,11 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
       if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z))
         set_bits(s.status, ST_NONFINITE);
     }
-    if (__ballot(far) != 0ull && lane_id() == 0) *flag_next = 1;
+    // one wave covers atoms of one tile, hence of one replica
+    if (__ballot(far) != 0ull && lane_id() == 0) {
+      *flag_next = 1;
+      rflag_next[tl.rep] = 1;
+    }
   }
 }
 
@@ -886,7 +897,8 @@ __global__ __launch_bounds__(64) void k_halfkick(Geometry g, State s, double sca
 
 // Per atom: e_pot = 1/2 sum_j phi(r_ij) + F(rho_i) (Eq. potential, float64),
 // e_kin = 1/2 m |v|^2 / ftm2v with on-step v = v_half + vscale F.  Each block
-// reduces its tile in a fixed tree order into partial[blockIdx].
+// reduces its tile in a fixed tree order into partial[replica tile number],
+// so a replica's sums do not depend on the other replicas of the batch.
 __global__ __launch_bounds__(64) void k_energy_atoms(Geometry g, State s, Tables t, double mass_over,
                                                      double vscale) {
   __shared__ double s_e[64], s_k[64];
@@ -939,23 +951,23 @@ __global__ __launch_bounds__(64) void k_energy_atoms(Geometry g, State s, Tables
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    s.partial[2 * blockIdx.x] = s_e[0];
-    s.partial[2 * blockIdx.x + 1] = s_k[0];
+  if (threadIdx.x == 0 && tl.count > 0) {
+    const RepDev& rp = g.reps[tl.rep];
+    const int64_t slot = rp.tile0 + (tl.begin - rp.atom0) / 64;
+    s.partial[2 * slot] = s_e[0];
+    s.partial[2 * slot + 1] = s_k[0];
   }
 }
 
-// One block per replica: add the tile partials of replica r in tile order.
+// One block per replica: add the tile partials of replica r in its tile order.
 __global__ __launch_bounds__(256) void k_energy_reduce(Geometry g, State s, double* out) {
   __shared__ double s_e[256], s_k[256];
   const int r = blockIdx.x;
+  const RepDev& rp = g.reps[r];
   double e = 0.0, k = 0.0;
-  for (int b = threadIdx.x; b < g.n_atiles; b += 256) {
-    const AtomTile tl = g.atiles[b];
-    if (tl.rep == r && tl.count > 0) {
-      e += s.partial[2 * b];
-      k += s.partial[2 * b + 1];
-    }
+  for (int b = threadIdx.x; b < rp.ntiles; b += 256) {
+    e += s.partial[2 * (rp.tile0 + b)];
+    k += s.partial[2 * (rp.tile0 + b) + 1];
   }
   s_e[threadIdx.x] = e;
   s_k[threadIdx.x] = k;
@@ -1023,20 +1035,23 @@ hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_tot
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond) {
-  hipLaunchKernelGGL(k_bin, dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, cond);
+hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
+                      const int32_t* rcond) {
+  hipLaunchKernelGGL(k_bin, dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, cond, rcond);
   return hipGetLastError();
 }
 
-hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond) {
-  hipLaunchKernelGGL(k_build, dim3(L.ctile_blocks), dim3(kBuildBlock), 0, L.stream, g, s, cond);
+hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
+                        const int32_t* rcond) {
+  hipLaunchKernelGGL(k_build, dim3(L.ctile_blocks), dim3(kBuildBlock), 0, L.stream, g, s, cond,
+                     rcond);
   return hipGetLastError();
 }
 
 hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64_t m) {
   hipError_t e;
   if ((e = launch_zero_bins(L, s, m)) != hipSuccess) return e;
-  if ((e = launch_bin(L, g, s, nullptr)) != hipSuccess) return e;
+  if ((e = launch_bin(L, g, s, nullptr, nullptr)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, L.stream, s.bin_cnt, s.cell_start, m,
                      g.cell_cap);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1066,19 +1081,20 @@ size_t force_lds_bytes(const Tables& t, int prec) {
 
 template <int PREC, int LPA>
 static hipError_t density_go(const Launch& L, const Geometry& g, const State& s, const Tables& t,
-                             double4* pos, const int32_t* cz, int32_t* cf, int64_t m, int want) {
+                             double4* pos, const int32_t* cz, int32_t* cf, int32_t* rc, int64_t m,
+                             int want) {
   hipLaunchKernelGGL((k_density<PREC, LPA>), dim3(2 * L.persist_blocks),
                      dim3(pair_threads(PREC, false, LPA)), density_lds_bytes(t, PREC), L.stream, g,
-                     s, t, pos, cz, cf, m, want);
+                     s, t, pos, cz, cf, rc, m, want);
   return hipGetLastError();
 }
 
 template <int PREC, int LPA>
 static hipError_t force_int_go(const Launch& L, const Geometry& g, const State& s, const Tables& t,
-                               const double4* pi, double4* po, int32_t* fl) {
+                               const double4* pi, double4* po, int32_t* fl, int32_t* rfl) {
   hipLaunchKernelGGL((k_force_integrate<PREC, LPA>), dim3(L.persist_blocks),
                      dim3(pair_threads(PREC, true, LPA)), force_lds_bytes(t, PREC), L.stream, g, s,
-                     t, pi, po, fl);
+                     t, pi, po, fl, rfl);
   return hipGetLastError();
 }
 
@@ -1101,10 +1117,12 @@ static hipError_t force_only_go(const Launch& L, const Geometry& g, const State&
 
 hipError_t launch_density(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                           int precision, int lpa, const double4* pos, const int32_t* cond_zero,
-                          int32_t* clear_flag, int64_t n_cells_total, bool want_rho) {
+                          int32_t* clear_flag, int32_t* rclear, int64_t n_cells_total,
+                          bool want_rho) {
   double4* p = const_cast<double4*>(pos);
   const int w = want_rho ? 1 : 0;
-#define MDK_D(P, Lp) density_go<P, Lp>(L, g, s, t, p, cond_zero, clear_flag, n_cells_total, w)
+#define MDK_D(P, Lp) \
+  density_go<P, Lp>(L, g, s, t, p, cond_zero, clear_flag, rclear, n_cells_total, w)
   if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_D) }
   MDK_LPA_SWITCH(1, lpa, MDK_D)
 #undef MDK_D
@@ -1112,8 +1130,8 @@ hipError_t launch_density(const Launch& L, const Geometry& g, const State& s, co
 
 hipError_t launch_force_integrate(const Launch& L, const Geometry& g, const State& s,
                                   const Tables& t, int precision, int lpa, const double4* pos_in,
-                                  double4* pos_out, int32_t* flag_next) {
-#define MDK_F(P, Lp) force_int_go<P, Lp>(L, g, s, t, pos_in, pos_out, flag_next)
+                                  double4* pos_out, int32_t* flag_next, int32_t* rflag_next) {
+#define MDK_F(P, Lp) force_int_go<P, Lp>(L, g, s, t, pos_in, pos_out, flag_next, rflag_next)
   if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_F) }
   MDK_LPA_SWITCH(1, lpa, MDK_F)
 #undef MDK_F

@@ -1,0 +1,69 @@
+"""Batched replicas: each replica of a batch equals the same replica run alone
+(bitwise, same schedule) and follows the oracle trajectory."""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import configs, potential as P
+
+pytestmark = pytest.mark.gpu
+RC, SKIN = P.RC, configs.SKIN
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _replicas(n_rep):
+    reps = []
+    for r in range(n_rep):
+        rng = np.random.default_rng([40, r])
+        n = int(rng.integers(5, 9))
+        reps.append(configs.make_box(n, rng, vacancy_fraction=float(rng.uniform(0, 0.02)),
+                                     temperature=float(rng.uniform(300, 2000))))
+    return reps
+
+
+def _params(md, lpa):
+    return md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN,
+                          ftm2v=configs.FTM2V, chunk_steps=20, lanes_per_atom=lpa)
+
+
+@pytest.mark.parametrize("lpa", [1, 4])
+def test_batch_equals_alone_and_oracle(oracle_lib, lpa):
+    import torch
+
+    from paper_2405_07898_amd import md
+
+    assert torch.cuda.is_available()
+    tabs = P.md_tables()
+    reps = _replicas(5)
+    steps = 61
+    _say(f"[gpu] batch of {len(reps)} replicas sizes {[b.n for b in reps]} lpa={lpa}")
+    batch = md.System(_params(md, lpa), tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
+    batch.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
+    batch.build_neighbors()
+    batch.step(steps)
+    xb, vb, fb = (t.cpu().numpy() for t in batch.get_state())
+    peb, keb = batch.energy()
+    batch.close()
+    off = np.concatenate([[0], np.cumsum([b.n for b in reps])])
+    for r, b in enumerate(reps):
+        alone = md.System(_params(md, lpa), tabs, [b.n], b.box[None, :])
+        alone.set_state(b.x, b.v)
+        alone.build_neighbors()
+        alone.step(steps)
+        xa, va, fa = (t.cpu().numpy() for t in alone.get_state())
+        pea, kea = alone.energy()
+        alone.close()
+        sl = slice(off[r], off[r + 1])
+        assert np.array_equal(xb[sl], xa) and np.array_equal(vb[sl], va)
+        assert np.array_equal(fb[sl], fa)
+        assert peb[r] == pea[0] and keb[r] == kea[0]
+        out = oracle_lib.md_run(b.x, b.v, b.box, tabs, steps, mass=configs.MASS, dt=configs.DT,
+                                r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+        d = xa - out["x"]
+        d -= b.box * np.round(d / b.box)
+        assert np.max(np.abs(d)) < 1e-9, (r, np.max(np.abs(d)))
