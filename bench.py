@@ -135,6 +135,104 @@ def cpu_baseline(box, tabs, budget_s: float = 15.0):
                 atom_steps_per_s=steps * box.n / dt)
 
 
+def bench_small(torch, md, configs, tabs):
+    """2,000-atom box, 100-step graph chunks (launch-latency regime)."""
+    box = configs.config_small()
+    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    lpa, _ = s.autotune(10)
+    s.step(100)
+    sec, _ = time_steps(torch, s, 2000)
+    st = s.stats()
+    s.close()
+    return {"n_atoms": box.n, "steps": 2000, "timesteps_per_s": round(2000 / sec, 1),
+            "atom_steps_per_s": round(2000 / sec * box.n, 1), "lanes_per_atom": lpa,
+            "rebuilds": st["rebuilds"]}
+
+
+def bench_batched(torch, md, configs, tabs, args):
+    """256 replicas (5-20 cells, 0-2 % vacancies, 300-2000 K) in one launch per pass,
+    against a sequential loop of single-replica contexts."""
+    from workloads import potential
+
+    reps = configs.config_batch(256)
+    n_tot = sum(b.n for b in reps)
+    res = {"n_replicas": len(reps), "n_atoms_total": n_tot}
+    for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
+        p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC,
+                           skin=configs.SKIN, ftm2v=configs.FTM2V, precision=prec,
+                           chunk_steps=100, nbr_capacity=128, cell_capacity=64)
+        s = md.System(p, tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
+        s.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
+        s.build_neighbors()
+        lpa, _ = s.autotune(5)
+        s.step(100)
+        steps = args.batched_steps
+        sec, _ = time_steps(torch, s, steps)
+        s.close()
+        res[name] = {"steps": steps, "lanes_per_atom": lpa,
+                     "timesteps_per_s": round(steps / sec, 2),
+                     "atom_steps_per_s": round(steps * n_tot / sec, 1)}
+    # sequential per-replica loop (float64), same kernels, one context per replica
+    seq_steps = args.sequential_steps
+    systems = []
+    for b in reps:
+        p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC,
+                           skin=configs.SKIN, ftm2v=configs.FTM2V, chunk_steps=50,
+                           nbr_capacity=128, cell_capacity=64)
+        s = md.System(p, tabs, [b.n], b.box[None, :])
+        s.set_state(b.x, b.v)
+        s.build_neighbors()
+        s.step(50)
+        systems.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in systems:
+        s.step(seq_steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    for s in systems:
+        s.close()
+    res["sequential_fp64"] = {"steps_per_replica": seq_steps,
+                              "atom_steps_per_s": round(seq_steps * n_tot / sec, 1)}
+    res["batched_over_sequential_fp64"] = round(
+        res["fp64"]["atom_steps_per_s"] / res["sequential_fp64"]["atom_steps_per_s"], 2)
+    return res
+
+
+def bench_fm(torch, md, configs, potential, tabs):
+    """Force-matching gradient evaluations (forward + adjoint) over 64 x 2,000 atoms."""
+    from paper_2405_07898_amd import fm
+
+    boxes = configs.config_fm(64, 10)
+    x = np.concatenate([b.x for b in boxes])
+    # reference forces from the library's float64 pass with the 2000-knot tables
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=0.0,
+                       ftm2v=configs.FTM2V)
+    s = md.System(p, tabs, [b.n for b in boxes], np.stack([b.box for b in boxes]))
+    s.set_state(x, np.zeros_like(x))
+    s.build_neighbors()
+    fref, _, _ = s.compute_forces()
+    s.close()
+    ftabs = potential.fm_tables()
+    prob = fm.ForceMatch(x, fref, [b.n for b in boxes], np.stack([b.box for b in boxes]), ftabs)
+    coefs = [torch.as_tensor(t.coef, device="cuda") for t in ftabs]
+    for _ in range(3):
+        prob.forward(*coefs)
+        prob.backward()
+    reps = 50
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.forward(*coefs)
+        prob.backward()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    prob.close()
+    return {"n_configs": 64, "n_atoms_total": int(x.shape[0]),
+            "gradient_evaluations_per_s": round(reps / sec, 2),
+            "ms_per_gradient_evaluation": round(sec / reps * 1e3, 4)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +243,8 @@ def main() -> int:
     ap.add_argument("--secondary-steps", type=int, default=1000)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--lpa", type=int, default=0)
+    ap.add_argument("--batched-steps", type=int, default=300)
+    ap.add_argument("--sequential-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the EAM path here is built and timed on a "
@@ -256,6 +356,14 @@ def main() -> int:
             log(f"  {sec_out[name]}")
         out["secondary_810k"] = {"n_atoms": big.n, "steps": args.secondary_steps,
                                  "workload": "74^3 BCC sites - 1% vacancies, 2500 K", **sec_out}
+
+    if not args.no_secondary:
+        out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)
+        log(f"  small: {out['secondary_small_2000']}")
+        out["secondary_batched_256"] = bench_batched(torch, md, configs, tabs, args)
+        log(f"  batched: {out['secondary_batched_256']}")
+        out["secondary_force_matching"] = bench_fm(torch, md, configs, potential, tabs)
+        log(f"  force matching: {out['secondary_force_matching']}")
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
