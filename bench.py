@@ -98,19 +98,37 @@ def time_steps(torch, s, steps: int) -> float:
 
 
 def time_kernel(torch, s, md, which: int, reps: int) -> float:
-    """Average duration (us) of one pass kernel: per-launch event pairs on the
-    library's stream."""
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    """Average duration (us) of one pass kernel: `reps` back-to-back launches on
+    the library's stream between one pair of events, divided by `reps`."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     s.launch_pass(which, 2)  # warm
     s.stream.synchronize()
-    for k in range(reps):
-        starts[k].record(s.stream)
-        s.launch_pass(which, 1)
-        ends[k].record(s.stream)
+    e0.record(s.stream)
+    s.launch_pass(which, reps)
+    e1.record(s.stream)
     s.stream.synchronize()
-    d = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)]) * 1e3
-    return float(np.mean(d)), float(np.median(d))
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def copy_probe(torch, mib: int, reps: int = 5) -> dict:
+    """A plain elementwise copy (y = -x, float64) of known size: it reads and
+    writes mib MiB once per launch, so hardware byte counters read on it give
+    the factor between counter units and bytes moved."""
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "launches": reps,
+            "avg_us": round(us, 2), "gbs": round(2 * n * 8 / (us * 1e-6) / 1e9, 1)}
 
 
 def cpu_baseline(box, tabs, budget_s: float = 15.0):
@@ -245,6 +263,8 @@ def main() -> int:
     ap.add_argument("--lpa", type=int, default=0)
     ap.add_argument("--batched-steps", type=int, default=300)
     ap.add_argument("--sequential-steps", type=int, default=20)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the EAM path here is built and timed on a "
@@ -280,8 +300,8 @@ def main() -> int:
         f"rebuilds {st1['rebuilds'] - st0['rebuilds']}, mean list {n_l:.2f}")
 
     # dominant kernel: force + integrate, timed per launch on the library stream
-    dens_us, dens_med = time_kernel(torch, s, md, md.PASS_DENSITY, args.kernel_reps)
-    force_us, force_med = time_kernel(torch, s, md, md.PASS_FORCE_RAW, args.kernel_reps)
+    dens_us = time_kernel(torch, s, md, md.PASS_DENSITY, args.kernel_reps)
+    force_us = time_kernel(torch, s, md, md.PASS_FORCE_RAW, args.kernel_reps)
     byts = force_pass_bytes(box.n, n_l, False)
     flops = force_pass_flops(box.n, n_l, n_l)
     gbs = byts / (force_us * 1e-6) / 1e9
@@ -297,7 +317,7 @@ def main() -> int:
             "frac": round((gbs / HBM_PEAK_GBS) if bound == "hbm" else (tfl / FP64_PEAK_TFLOPS), 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": byts, "algorithmic_flops_per_launch": flops,
-            "avg_kernel_us": round(force_us, 3), "median_kernel_us": round(force_med, 3),
+            "avg_kernel_us": round(force_us, 3),
             "alu_frac": round(tfl / FP64_PEAK_TFLOPS, 4), "mean_list_length": round(n_l, 3),
             "density_kernel_us": round(dens_us, 3)}
     log(f"force pass {force_us:.2f} us -> {gbs:.0f} GB/s ({roof['frac'] * 100:.1f}% HBM), "
@@ -332,7 +352,7 @@ def main() -> int:
             t2, _ = time_steps(torch, sb, args.secondary_steps)
             stb = sb.stats()
             nlb = stb["list_entries"] / big.n
-            fu, _ = time_kernel(torch, sb, md, md.PASS_FORCE_RAW, 50)
+            fu = time_kernel(torch, sb, md, md.PASS_FORCE_RAW, 50)
             b2 = force_pass_bytes(big.n, nlb, prec == md.MD_MIXED)
             sec_out[name] = {"timesteps_per_s": round(args.secondary_steps / t2, 2),
                              "atom_steps_per_s": round(args.secondary_steps / t2 * big.n, 1),
@@ -364,6 +384,10 @@ def main() -> int:
         log(f"  batched: {out['secondary_batched_256']}")
         out["secondary_force_matching"] = bench_fm(torch, md, configs, potential, tabs)
         log(f"  force matching: {out['secondary_force_matching']}")
+
+    if args.copy_probe_mib > 0:
+        out["copy_probe"] = copy_probe(torch, args.copy_probe_mib)
+        log(f"copy probe: {out['copy_probe']}")
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

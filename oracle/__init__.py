@@ -47,7 +47,8 @@ class MDStats(C.Structure):
 
 class Analytic(C.Structure):
     _fields_ = [("rc", C.c_double), ("r0", C.c_double), ("phi_a", C.c_double),
-                ("phi_b", C.c_double), ("rho_b", C.c_double), ("emb_a", C.c_double)]
+                ("phi_b", C.c_double), ("rho_b", C.c_double), ("emb_a", C.c_double),
+                ("well_w", C.c_double), ("well_s", C.c_double), ("well_r", C.c_double)]
 
 
 _lib = None
@@ -239,11 +240,14 @@ def forces_at(x, box, tables, rc, skin=0.0, cap=256):
     return dict(f=f, rho=r, fp=fp, pe=pe.value, flags=code)
 
 
-def forces_analytic(x, box, rc=5.0, r0=2.86, phi_a=0.3, phi_b=8.0, rho_b=6.0, emb_a=2.0):
+def forces_analytic(x, box, params):
+    """Forces and energy of the closed-form potential; params holds rc, r0, phi_a,
+    phi_b, rho_b, emb_a, well_w, well_s, well_r (the synthetic potential's constants)."""
     x = _f64(x)
     f = np.empty_like(x)
     pe = C.c_double()
-    an = Analytic(rc, r0, phi_a, phi_b, rho_b, emb_a)
+    an = Analytic(*[float(params[k]) for k in ("rc", "r0", "phi_a", "phi_b", "rho_b", "emb_a",
+                                                "well_w", "well_s", "well_r")])
     code = lib().or_forces_analytic(x.shape[0], _pd(x), _pd(_f64(box)), C.byref(an), _pd(f),
                                     C.byref(pe))
     if code != OR_OK:

@@ -18,7 +18,7 @@ def _problem(oracle_lib, boxes):
     x = np.concatenate([b.x for b in boxes])
     off = np.concatenate([[0], np.cumsum([b.n for b in boxes])]).astype(np.int64)
     bx = np.stack([b.box for b in boxes])
-    fref = np.concatenate([oracle_lib.forces_analytic(b.x, b.box)[0] for b in boxes])
+    fref = np.concatenate([oracle_lib.forces_analytic(b.x, b.box, P.analytic_params())[0] for b in boxes])
     return x, off, bx, fref
 
 

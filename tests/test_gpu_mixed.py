@@ -4,8 +4,11 @@ state) against the float64 oracle on identical positions.
 Bound: each pair term carries a relative error of at most about 16 u
 (u = 2^-24: rounding of the separation, r^2, the hardware rsqrt, the
 spline segment and the products), and the TwoSum accumulation adds
-O(n u^2).  So |dF_i| <= 16 u sum_j |f_ij| with f_ij the pair force, and
-|d rho_i| <= 16 u rho_i.  sum_j |f_ij| is computed here by numpy from the
+O(n u^2).  The pair force f_ij = (F'_i + F'_j) rho'(r) + phi'(r) is a sum of
+an embedding and a pair term that cancel in part (exactly so in the
+lattice-sum sense at zero pressure), and each carries its error relative to
+its own size, so |dF_i| <= 16 u sum_j (|(F'_i + F'_j) rho'(r_ij)| + |phi'(r_ij)|)
+and |d rho_i| <= 16 u rho_i.  The sums are computed here by numpy from the
 analytic potential (a bound on the tabulated one within 1e-6)."""
 import sys
 
@@ -31,7 +34,7 @@ def _pair_force_sums(x, box, fp):
     np.fill_diagonal(r, np.inf)
     m = r < RC
     rr = np.where(m, r, 1.0)
-    s = np.where(m, np.abs((fp[:, None] + fp[None, :]) * P.drho(rr) + P.dphi(rr)), 0.0)
+    s = np.where(m, np.abs((fp[:, None] + fp[None, :]) * P.drho(rr)) + np.abs(P.dphi(rr)), 0.0)
     return s.sum(1) * 1.000001
 
 

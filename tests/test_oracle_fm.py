@@ -19,7 +19,7 @@ def fm_problem(oracle_lib):
     x = np.concatenate([b.x for b in boxes])
     off = np.array([0, boxes[0].n, boxes[0].n + boxes[1].n], np.int64)
     bx = np.stack([b.box for b in boxes])
-    fref = np.concatenate([oracle_lib.forces_analytic(b.x, b.box)[0] for b in boxes])
+    fref = np.concatenate([oracle_lib.forces_analytic(b.x, b.box, P.analytic_params())[0] for b in boxes])
     tabs = P.fm_tables()
     return dict(x=x, off=off, boxes=bx, fref=fref, tabs=tabs)
 

@@ -35,14 +35,28 @@ def test_spline_tables_match_analytic(oracle_lib, md_tables):
     r = np.linspace(1.5, 4.999, 20001)
     for tab, f, df in ((phi_t, P.phi, P.dphi), (rho_t, P.rho, P.drho)):
         v, d, _ = oracle_lib.spline_eval(tab, r)
-        assert np.max(np.abs(v - f(r))) < 2e-10
-        assert np.max(np.abs(d - df(r))) < 2e-7
+        # cubic-spline interpolation bounds (Hall and Meyer, 1976):
+        # |s - f| <= 5/384 h^4 max|f''''|, |s' - f'| <= 1/24 h^3 max|f''''|
+        q = 1e-3
+        rr = np.linspace(1.5 - 2 * q, 5.0 - 2 * q, 7001)
+        f4 = np.max(np.abs(f(rr - 2 * q) - 4 * f(rr - q) + 6 * f(rr) - 4 * f(rr + q)
+                           + f(rr + 2 * q))) / q ** 4
+        h = tab.dx
+        assert np.max(np.abs(v - f(r))) < 5.0 / 384.0 * h ** 4 * f4 * 1.01
+        assert np.max(np.abs(d - df(r))) < h ** 3 * f4 / 24.0 * 1.01
     p = np.linspace(0.5, 39.99, 20001)
     v, d, dd = oracle_lib.spline_eval(emb_t, p)
-    # natural end condition (F'' = 0 at rho = 40 while the true F'' is 2e-3) costs ~4e-8
-    assert np.max(np.abs(v - P.emb(p))) < 5e-8
-    assert np.max(np.abs(d - P.demb(p))) < 5e-6
-    assert np.max(np.abs(dd - P.ddemb(p))[p > 1.0]) < 1e-3
+    # Two error sources.  Interior: the Hall-Meyer bounds with max|F''''| on
+    # [0.5, 40] (value, slope) or [1, 40] (curvature, 3/8 h^2 max|F''''|).  End:
+    # the natural condition sets s'' = 0 at rho = 40 where F'' = M; that moment
+    # defect, spread over the last interval, moves s by at most M h^2 (t^3 - t)/6
+    # (max 0.065 M h^2), s' by M h / 3 and s'' by M.
+    h = emb_t.dx
+    m_end = abs(float(P.ddemb(emb_t.x1)))
+    f4 = lambda lo: 15.0 / 16.0 * P.EMB_A * lo ** -3.5  # F = -A sqrt(rho): |F''''| largest at lo
+    assert np.max(np.abs(v - P.emb(p))) < 0.065 * m_end * h ** 2 + 5.0 / 384.0 * h ** 4 * f4(0.5)
+    assert np.max(np.abs(d - P.demb(p))) < m_end * h / 3.0 + h ** 3 * f4(0.5) / 24.0
+    assert np.max(np.abs(dd - P.ddemb(p))[p > 1.0]) < m_end + 3.0 / 8.0 * h ** 2 * f4(1.0)
 
 
 def test_spline_knots_interpolate(oracle_lib, md_tables):
@@ -231,7 +245,7 @@ def test_linear_embedding_reduces_to_pair_potential(oracle_lib):
 def test_tabulated_forces_match_analytic(oracle_lib, md_tables):
     b = configs.small_box(6, seed=13, sigma_x=0.08)
     res = oracle_lib.forces_at(b.x, b.box, md_tables, RC, SKIN)
-    fa, ea = oracle_lib.forces_analytic(b.x, b.box)
+    fa, ea = oracle_lib.forces_analytic(b.x, b.box, P.analytic_params())
     assert np.max(np.abs(res["f"] - fa)) < 5e-6
     assert abs(res["pe"] - ea) < 1e-6
 

@@ -7,10 +7,17 @@ evaluates the EAM energy or forces of a configuration.
 
 Analytic forms (units: Angstrom, eV):
     fc(r)   = (1 - (r/rc)^2)^3            for r < rc, else 0
-    phi(r)  = 0.3 * exp(-8 (r/r0 - 1)) * fc(r)
+    phi(r)  = (A exp(-8 (r/r0 - 1)) - W exp(-((r - a)/s)^2)) * fc(r)
     rho(r)  = exp(-6 (r/r0 - 1)) * fc(r)
-    F(rho)  = -2 * sqrt(rho)
-with rc = 5.0 and r0 = 2.86.
+    F(rho)  = -3 * sqrt(rho)
+with rc = 5.0, r0 = 2.86 (the first-neighbour distance of BCC at a = 3.304),
+A = 1.5514, and a shallow well W = 0.14 eV, s = 0.2 A centred on the
+second-neighbour distance a.  A sets zero pressure for BCC at a = 3.304; the
+well makes the tetragonal shear modulus positive (without it the BCC lattice
+shears towards close packing and the crystal collapses and heats).  Per-atom
+lattice-sum curvatures at a = 3.304 (eV per unit linear strain squared):
+hydrostatic 197.5, tetragonal 72.6, monoclinic 22.7; a solid at 300 K keeps
+its 26 neighbours inside rc.
 
 Table layout (shared convention of both consumers): a spline with n knots on
 [x0, x0 + (n-1)*dx] stores, for every segment k in [0, n-2], four coefficients
@@ -27,10 +34,13 @@ from scipy.interpolate import CubicSpline
 
 RC = 5.0
 R0 = 2.86
-PHI_A = 0.3
+PHI_A = 1.5514
 PHI_B = 8.0
+WELL_W = 0.14
+WELL_S = 0.2
+WELL_R = 3.304
 RHO_B = 6.0
-EMB_A = 2.0
+EMB_A = 3.0
 RHO_MAX = 40.0
 N_KNOTS_MD = 2000
 
@@ -56,6 +66,12 @@ class SplineTable:
         return self.x0 + (self.n_knots - 1) * self.dx
 
 
+def analytic_params() -> dict:
+    """The constants above, for evaluators of the closed forms."""
+    return dict(rc=RC, r0=R0, phi_a=PHI_A, phi_b=PHI_B, rho_b=RHO_B, emb_a=EMB_A,
+                well_w=WELL_W, well_s=WELL_S, well_r=WELL_R)
+
+
 # --- analytic functions (vectorised numpy) ---------------------------------
 
 def fc(r):
@@ -70,13 +86,24 @@ def dfc(r):
     return np.where(r < RC, 3.0 * u ** 2 * (-2.0 * r / RC ** 2), 0.0)
 
 
+def _pair_core(r):
+    r = np.asarray(r, dtype=np.float64)
+    return PHI_A * np.exp(-PHI_B * (r / R0 - 1.0)) - WELL_W * np.exp(-((r - WELL_R) / WELL_S) ** 2)
+
+
+def _dpair_core(r):
+    r = np.asarray(r, dtype=np.float64)
+    u = (r - WELL_R) / WELL_S
+    return (PHI_A * (-PHI_B / R0) * np.exp(-PHI_B * (r / R0 - 1.0))
+            + WELL_W * (2.0 * u / WELL_S) * np.exp(-u ** 2))
+
+
 def phi(r):
-    return PHI_A * np.exp(-PHI_B * (np.asarray(r) / R0 - 1.0)) * fc(r)
+    return _pair_core(r) * fc(r)
 
 
 def dphi(r):
-    e = PHI_A * np.exp(-PHI_B * (np.asarray(r) / R0 - 1.0))
-    return e * (-PHI_B / R0) * fc(r) + e * dfc(r)
+    return _dpair_core(r) * fc(r) + _pair_core(r) * dfc(r)
 
 
 def rho(r):
