@@ -27,6 +27,9 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_2405_07898_amd", "csrc", "md_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_integrate_128k_traffic.json")
+# re-sort atoms by cell every 10 graph chunks (1,000 steps): atoms of a solid stay
+# near their sites, so cell order decays slowly
+SORT_EVERY = 10
 
 
 def log(msg: str) -> None:
@@ -73,7 +76,7 @@ def make_system(md, box, tabs, *, precision, chunk, lpa=0):
 
     p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
                        ftm2v=configs.FTM2V, precision=precision, chunk_steps=chunk,
-                       lanes_per_atom=lpa, nbr_capacity=128, cell_capacity=64, sort_every=1)
+                       lanes_per_atom=lpa, nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY)
     s = md.System(p, tabs, [box.n], box.box[None, :])
     s.set_state(box.x, box.v)
     s.build_neighbors()
@@ -157,7 +160,7 @@ def bench_small(torch, md, configs, tabs):
     """2,000-atom box, 100-step graph chunks (launch-latency regime)."""
     box = configs.config_small()
     s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
-    lpa, _ = s.autotune(10)
+    lpa, _ = s.autotune(50)
     s.step(100)
     sec, _ = time_steps(torch, s, 2000)
     st = s.stats()
@@ -182,7 +185,7 @@ def bench_batched(torch, md, configs, tabs, args):
         s = md.System(p, tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
         s.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
         s.build_neighbors()
-        lpa, _ = s.autotune(5)
+        lpa, _ = s.autotune(20)
         s.step(100)
         steps = args.batched_steps
         sec, _ = time_steps(torch, s, steps)
@@ -284,7 +287,7 @@ def main() -> int:
     log(f"workload 128k: n={box.n} box={box.box[0]:.3f} A; building")
     s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100, lpa=args.lpa)
     if args.lpa == 0:
-        lpa, us = s.autotune(10)
+        lpa, us = s.autotune(50)
         log(f"autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
     pe0, ke0 = s.energy()
     log(f"warmup {args.warmup} steps")
@@ -346,7 +349,7 @@ def main() -> int:
             log(f"secondary 810k {name}: n={big.n}")
             sb = make_system(md, big, tabs, precision=prec, chunk=100, lpa=args.lpa)
             if args.lpa == 0:
-                lpa, us = sb.autotune(5)
+                lpa, us = sb.autotune(20)
                 log(f"  autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
             sb.step(100)
             t2, _ = time_steps(torch, sb, args.secondary_steps)

@@ -176,10 +176,13 @@ md_status md_launch_pass(md_ctx* ctx, int32_t pass, int32_t reps);
  * identical up to that reduction order.  Drops the captured step graph. */
 md_status md_set_schedule(md_ctx* ctx, int32_t lanes_per_atom);
 
-/* Autotuner: times reps rounds of the density and force passes at the
- * current state for every lanes-per-atom choice (HIP events on the context
- * stream), keeps the fastest and reports it (either pointer may be NULL).
- * Leaves the state unchanged.  Requires md_build_neighbors. */
+/* Autotuner: times reps rounds of the step's density and force-plus-update
+ * kernels at the current state for every lanes-per-atom choice (HIP events on
+ * the context stream, two sweeps, the faster sweep of each choice kept),
+ * keeps the fastest and reports it in microseconds per round (either pointer
+ * may be NULL).  Positions, velocities and the step count come back from the
+ * rollback snapshot, which then holds the current state.  Requires
+ * md_build_neighbors. */
 md_status md_autotune(md_ctx* ctx, int32_t reps, int32_t* best_lanes_per_atom, float* best_us);
 
 /* Last error text of this context (or of the library when ctx is NULL). */

@@ -830,38 +830,53 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
   HIPC(c, hipEventCreate(&e0));
   HIPC(c, hipEventCreate(&e1));
   const int cand[4] = {1, 2, 4, 8};
-  float best = 3.4e38f;
-  int pick = c->lpa;
+  float per[4] = {3.4e38f, 3.4e38f, 3.4e38f, 3.4e38f};
   md_status rc = MD_OK;
-  for (int q = 0; q < 4 && rc == MD_OK; ++q) {
-    const int l = cand[q];
-    // one untimed round, then reps timed rounds of density + forces (the
-    // same pair code the step uses; forces go to the scratch force buffer)
-    for (int r = 0; r <= reps && rc == MD_OK; ++r) {
-      if (r == 1) {
-        hipError_t e = hipEventRecord(e0, c->L.stream);
-        if (e != hipSuccess) rc = hip_fail(c, e, "hipEventRecord");
+  // the step's own kernels (density, then forces with the integration) on the
+  // current state; velocities and positions come back from a snapshot after
+  // the sweeps, and the rebuild flags written go to scratch words
+  HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, false));
+  // two sweeps over the candidates, keeping each one's faster sweep
+  for (int sweep = 0; sweep < 2 && rc == MD_OK; ++sweep) {
+    for (int q = 0; q < 4 && rc == MD_OK; ++q) {
+      const int l = cand[q];
+      // one untimed round, then reps timed rounds
+      for (int r = 0; r <= reps && rc == MD_OK; ++r) {
+        if (r == 1) {
+          hipError_t e = hipEventRecord(e0, c->L.stream);
+          if (e != hipSuccess) rc = hip_fail(c, e, "hipEventRecord");
+        }
+        hipError_t e = launch_density(c->L, c->g, s, c->t, c->p.precision, l, s.pos, nullptr,
+                                      nullptr, nullptr, c->sz.cells, false);
+        if (e == hipSuccess)
+          e = launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, l, s.pos,
+                                     c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
+                                     s.rflag + 2 * c->n_rep);
+        if (e != hipSuccess) rc = hip_fail(c, e, "autotune launch");
       }
-      hipError_t e = launch_density(c->L, c->g, s, c->t, c->p.precision, l, s.pos, nullptr,
-                                    nullptr, nullptr, c->sz.cells, false);
-      if (e == hipSuccess) e = launch_force_only(c->L, c->g, s, c->t, c->p.precision, l, s.pos);
-      if (e != hipSuccess) rc = hip_fail(c, e, "autotune launch");
-    }
-    if (rc != MD_OK) break;
-    float ms = 0.f;
-    hipError_t e = hipEventRecord(e1, c->L.stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      rc = hip_fail(c, e, "autotune timing");
-      break;
-    }
-    const float us = 1000.f * ms / (float)reps;
-    if (us < best) {
-      best = us;
-      pick = l;
+      if (rc != MD_OK) break;
+      float ms = 0.f;
+      hipError_t e = hipEventRecord(e1, c->L.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(c, e, "autotune timing");
+        break;
+      }
+      per[q] = std::min(per[q], 1000.f * ms / (float)reps);
     }
   }
+  if (rc == MD_OK) {
+    hipError_t e = launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, true);
+    if (e != hipSuccess) rc = hip_fail(c, e, "autotune restore");
+  }
+  float best = 3.4e38f;
+  int pick = c->lpa;
+  for (int q = 0; q < 4; ++q)
+    if (per[q] < best) {
+      best = per[q];
+      pick = cand[q];
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != MD_OK) return rc;

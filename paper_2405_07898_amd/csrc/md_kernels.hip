@@ -185,12 +185,10 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ p, int64
 // becomes 0), assign it to cell (cz*ny + cy)*nx + cx with
 // c_d = min(int(x_d * n_d/L_d), n_d - 1), append it to that cell's bin, and
 // snapshot the reference positions for the skin check.
-__global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* cond,
-                                            const int32_t* rcond) {
-  if (cond && *cond == 0) return;
-  if (has_error(s.status)) return;
-  if (cond && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
-  const AtomTile tl = g.atiles[blockIdx.x];
+// Launched with a grid smaller than the tile count (workgroup b takes tiles
+// b, b + G, ...), so that the launch that finds no rebuild due ends quickly.
+__device__ __forceinline__ void bin_tile(const Geometry& g, const State& s, const AtomTile& tl,
+                                         const int32_t* rcond) {
   if ((int)threadIdx.x >= tl.count) return;
   if (rcond && rcond[tl.rep] == 0) return;  // this replica keeps its list
   const RepDev& rp = g.reps[tl.rep];
@@ -242,6 +240,16 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
   else set_bits(s.status, ST_CELL_OVERFLOW);
 }
 
+__global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* cond,
+                                            const int32_t* rcond) {
+  // both words are read before either is tested: one memory latency, not two
+  const int32_t due = cond ? *cond : 1;
+  const bool err = has_error(s.status);
+  if (due == 0 || err) return;
+  if (cond && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
+  for (int b = blockIdx.x; b < g.n_atiles; b += gridDim.x) bin_tile(g, s, g.atiles[b], rcond);
+}
+
 // ============================================================ list build
 
 // One wave per cell.  The atoms of the 27 surrounding cells are gathered,
@@ -259,20 +267,30 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
 // list radius under either rule.
 constexpr int kBuildChunks = kMaxStage / 64;
 
-__global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t* cond,
-                                              const int32_t* rcond) {
-  if (cond && *cond == 0) return;
-  if (has_error(s.status)) return;
-  const CellTile ct = g.ctiles[blockIdx.x];
-  if (ct.cell < 0) return;
-  if (rcond && rcond[ct.rep] == 0) return;  // this replica keeps its list
+struct BuildLds {
+  int32_t q[27], n[27], off[28], code[27];
+  int32_t raw[kMaxStage];
+  int32_t idx[kMaxStage];
+  int8_t cell[kMaxStage];
+  int32_t center[kMaxCellCap], base[kMaxCellCap];
+  double cx[kMaxCellCap], cy[kMaxCellCap], cz[kMaxCellCap];
+};
+
+__device__ __forceinline__ void build_cell(const Geometry& g, const State& s, const CellTile& ct,
+                                           BuildLds& L) {
   const RepDev& rp = g.reps[ct.rep];
-  __shared__ int32_t s_q[27], s_n[27], s_off[28], s_code[27];
-  __shared__ int32_t s_raw[kMaxStage];
-  __shared__ int32_t s_idx[kMaxStage];
-  __shared__ int8_t s_cell[kMaxStage];
-  __shared__ int32_t s_center[kMaxCellCap], s_base[kMaxCellCap];
-  __shared__ double s_cx[kMaxCellCap], s_cy[kMaxCellCap], s_cz[kMaxCellCap];
+  int32_t* const s_q = L.q;
+  int32_t* const s_n = L.n;
+  int32_t* const s_off = L.off;
+  int32_t* const s_code = L.code;
+  int32_t* const s_raw = L.raw;
+  int32_t* const s_idx = L.idx;
+  int8_t* const s_cell = L.cell;
+  int32_t* const s_center = L.center;
+  int32_t* const s_base = L.base;
+  double* const s_cx = L.cx;
+  double* const s_cy = L.cy;
+  double* const s_cz = L.cz;
   const int lane = threadIdx.x;
   const int32_t nx = rp.nc[0], ny = rp.nc[1], nz = rp.nc[2];
   const int32_t c = ct.cell;
@@ -415,6 +433,24 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
   }
 }
 
+// Launched with a grid smaller than the cell count (workgroup b takes cell
+// tiles b, b + G, ...; G is a multiple of the XCD count, so every tile stays on
+// the XCD the tile table placed it on).
+__global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t* cond,
+                                              const int32_t* rcond) {
+  const int32_t due = cond ? *cond : 1;
+  const bool err = has_error(s.status);
+  if (due == 0 || err) return;
+  __shared__ BuildLds lds;
+  for (int b = blockIdx.x; b < g.n_ctiles; b += gridDim.x) {
+    const CellTile ct = g.ctiles[b];
+    if (ct.cell < 0) continue;
+    if (rcond && rcond[ct.rep] == 0) continue;  // this replica keeps its list
+    build_cell(g, s, ct, lds);
+    __syncthreads();  // the next cell reuses the staging arrays
+  }
+}
+
 // Fixed-order reduction of the per-cell build statistics into the status
 // block (longest list, fullest cell, total list entries).
 __global__ __launch_bounds__(1024) void k_cell_stats(State s, int64_t m) {
@@ -540,7 +576,8 @@ __device__ __forceinline__ double lane_sum_sym(double v) {
 
 // Neighbours are processed in batches of kBatch per lane: the list entries of
 // a batch are loaded together, then all their positions, then all their table
-// rows, so each batch pays the list -> position -> table latency chain once.
+// rows, so each batch pays the position -> table latency chain once; the list
+// entries of the next batch are requested while a batch is in flight.
 constexpr int kBatch = 4;
 
 // The spline rows of a pass live in LDS for the whole kernel: one persistent
@@ -610,9 +647,12 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
   float sum = 0.0f, comp = 0.0f;
   const double2* __restrict__ pos2 = reinterpret_cast<const double2*>(pos);
   const double* __restrict__ posd = reinterpret_cast<const double*>(pos);
-  for (int k0 = sub; k0 < m; k0 += LPA * kBatch) {
-    uint32_t e[kBatch];
-    load_entries<LPA>(s.nbr, N, (uint32_t)i, k0, m, self_e, e);
+  // the next batch's list entries are requested before this batch's
+  // positions are used, so the list latency hides behind the gather
+  const int kstep = LPA * kBatch;
+  uint32_t e[kBatch];
+  load_entries<LPA>(s.nbr, N, (uint32_t)i, sub, m, self_e, e);
+  for (int k0 = sub; k0 < m; k0 += kstep) {
     double2 qxy[kBatch];
     double qz[kBatch];
 #pragma unroll
@@ -621,6 +661,8 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
       qxy[u] = ld32(pos2, off);
       qz[u] = ld32(posd, off + 16u);
     }
+    uint32_t en[kBatch];
+    load_entries<LPA>(s.nbr, N, (uint32_t)i, k0 + kstep, m, self_e, en);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const bool v = k0 + u * LPA < m;
@@ -649,6 +691,8 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
         if (in) two_sum_acc(sum, comp, fmaf(fmaf(fmaf(c.w, tt, c.z), tt, c.y), tt, c.x));
       }
     }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) e[u] = en[u];
   }
   if (PREC == 0) return lane_sum_sym<LPA>(acc);
   lane_sum2<LPA>(sum, comp);
@@ -718,12 +762,15 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
   double ax = 0.0, ay = 0.0, az = 0.0;
   float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
   const float fpi = (float)pi.w;
-  for (int k0 = sub; k0 < m; k0 += LPA * kBatch) {
-    uint32_t e[kBatch];
-    load_entries<LPA>(s.nbr, N, (uint32_t)i, k0, m, self_e, e);
+  const int kstep = LPA * kBatch;
+  uint32_t e[kBatch];
+  load_entries<LPA>(s.nbr, N, (uint32_t)i, sub, m, self_e, e);
+  for (int k0 = sub; k0 < m; k0 += kstep) {
     double4 q[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) q[u] = ld32(pos, (e[u] & kIndexMask) * 32u);
+    uint32_t en[kBatch];
+    load_entries<LPA>(s.nbr, N, (uint32_t)i, k0 + kstep, m, self_e, en);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const bool v = k0 + u * LPA < m;
@@ -771,6 +818,8 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
         }
       }
     }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) e[u] = en[u];
   }
   if (PREC == 0) {
     fx = lane_sum_sym<LPA>(ax);
@@ -1037,14 +1086,15 @@ hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_tot
 
 hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                       const int32_t* rcond) {
-  hipLaunchKernelGGL(k_bin, dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, cond, rcond);
+  const int grid = std::min(L.atile_blocks, 4 * L.persist_blocks);
+  hipLaunchKernelGGL(k_bin, dim3(grid), dim3(64), 0, L.stream, g, s, cond, rcond);
   return hipGetLastError();
 }
 
 hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                         const int32_t* rcond) {
-  hipLaunchKernelGGL(k_build, dim3(L.ctile_blocks), dim3(kBuildBlock), 0, L.stream, g, s, cond,
-                     rcond);
+  const int grid = std::min(L.ctile_blocks, 12 * L.persist_blocks);
+  hipLaunchKernelGGL(k_build, dim3(grid), dim3(kBuildBlock), 0, L.stream, g, s, cond, rcond);
   return hipGetLastError();
 }
 
