@@ -11,7 +11,7 @@ namespace mdk {
 
 constexpr int kBlock = 256;          // threads per block of the per-atom passes
 constexpr int kBuildBlock = 64;      // one wave per cell in the list build
-constexpr int kMaxStage = 512;       // candidates staged in LDS per build batch
+constexpr int kMaxStage = 256;       // candidates staged per build batch (>= kMaxCellCap)
 constexpr int kMaxCellCap = 256;     // hard limit of cell_capacity
 constexpr int kMaxNbrCap = 1024;     // hard limit of nbr_capacity
 constexpr int kIndexBits = 26;       // list entry: j | image code << 26

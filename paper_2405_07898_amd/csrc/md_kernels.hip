@@ -267,35 +267,57 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
 // list radius under either rule.
 constexpr int kBuildChunks = kMaxStage / 64;
 
+// LDS of one build workgroup; the centre-cell arrays are sized by the cell
+// capacity at launch (dynamic shared memory).
 struct BuildLds {
-  int32_t q[27], n[27], off[28], code[27];
-  int32_t raw[kMaxStage];
-  int32_t idx[kMaxStage];
-  int8_t cell[kMaxStage];
-  int32_t center[kMaxCellCap], base[kMaxCellCap];
-  double cx[kMaxCellCap], cy[kMaxCellCap], cz[kMaxCellCap];
+  int32_t* q;       // [27] global cell index of each stencil cell
+  int32_t* n;       // [27] atoms in it (clamped to the capacity)
+  int32_t* off;     // [28] exclusive prefix of n
+  int32_t* code;    // [27] image code of the stencil cell
+  int32_t* raw;     // [kMaxStage] staged candidate ids, bin order
+  int32_t* idx;     // [kMaxStage] staged candidate ids, ordered per stencil cell
+  int32_t* center;  // [cap] centre atoms in increasing id
+  int32_t* base;    // [cap] list length so far of each centre atom
+  double* cx;       // [cap] centre positions
+  double* cy;
+  double* cz;
+  int8_t* cell;     // [kMaxStage] stencil cell of each staged slot
 };
 
+__host__ __device__ inline size_t build_lds_bytes(int ccap) {
+  return sizeof(int32_t) * (27 * 3 + 28 + 2 * (size_t)kMaxStage + 2 * (size_t)ccap) +
+         sizeof(double) * 3 * (size_t)ccap + (size_t)kMaxStage;
+}
+
+__device__ __forceinline__ BuildLds carve_build_lds(char* p, int ccap) {
+  BuildLds L;
+  // doubles first (8-byte aligned at the start of dynamic LDS)
+  L.cx = reinterpret_cast<double*>(p);
+  L.cy = L.cx + ccap;
+  L.cz = L.cy + ccap;
+  int32_t* w = reinterpret_cast<int32_t*>(L.cz + ccap);
+  L.q = w;
+  L.n = w + 27;
+  L.code = w + 54;
+  L.off = w + 81;
+  L.raw = w + 109;
+  L.idx = L.raw + kMaxStage;
+  L.center = L.idx + kMaxStage;
+  L.base = L.center + ccap;
+  L.cell = reinterpret_cast<int8_t*>(L.base + ccap);
+  return L;
+}
+
 __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, const CellTile& ct,
-                                           BuildLds& L) {
+                                           const BuildLds& L) {
   const RepDev& rp = g.reps[ct.rep];
-  int32_t* const s_q = L.q;
-  int32_t* const s_n = L.n;
-  int32_t* const s_off = L.off;
-  int32_t* const s_code = L.code;
-  int32_t* const s_raw = L.raw;
-  int32_t* const s_idx = L.idx;
-  int8_t* const s_cell = L.cell;
-  int32_t* const s_center = L.center;
-  int32_t* const s_base = L.base;
-  double* const s_cx = L.cx;
-  double* const s_cy = L.cy;
-  double* const s_cz = L.cz;
   const int lane = threadIdx.x;
   const int32_t nx = rp.nc[0], ny = rp.nc[1], nz = rp.nc[2];
   const int32_t c = ct.cell;
   const int32_t cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
   const int32_t ccap = g.cell_cap;
+  // stencil cells: lane k < 27 owns cell k (z-major, then y, then x)
+  int32_t n = 0;
   if (lane < 27) {
     const int dz = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dx = lane % 3 - 1;
     const int32_t ux = cx + dx, uy = cy + dy, uz = cz + dz;
@@ -304,32 +326,35 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
     const uint32_t ky = uy < 0 ? 0u : (uy >= ny ? 2u : 1u);
     const uint32_t kz = uz < 0 ? 0u : (uz >= nz ? 2u : 1u);
     const int32_t q = rp.cell0 + (((uz + nz) % nz) * ny + (uy + ny) % ny) * nx + (ux + nx) % nx;
-    int32_t n = s.bin_cnt[q];
-    if (n > ccap) n = ccap;
-    s_q[lane] = q;
-    s_n[lane] = n;
-    s_code[lane] = (int32_t)(kx | (ky << 2) | (kz << 4));
+    n = min(s.bin_cnt[q], ccap);
+    L.q[lane] = q;
+    L.n[lane] = n;
+    L.code[lane] = (int32_t)(kx | (ky << 2) | (kz << 4));
   }
-  __syncthreads();
-  if (lane == 0) {
-    s_off[0] = 0;
-    for (int k = 0; k < 27; ++k) s_off[k + 1] = s_off[k] + s_n[k];
+  // exclusive prefix of the 27 counts across the wave
+  int32_t incl = n;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
   }
+  if (lane < 27) L.off[lane] = incl - n;
+  if (lane == 26) L.off[27] = incl;
   __syncthreads();
   // centre atoms in increasing index, with their positions
-  const int32_t qc = s_q[13], n_c = s_n[13];
-  for (int u = lane; u < n_c; u += 64) s_raw[u] = s.bin_idx[(int64_t)qc * ccap + u];
+  const int32_t qc = L.q[13], n_c = L.n[13];
+  for (int u = lane; u < n_c; u += 64) L.raw[u] = s.bin_idx[(int64_t)qc * ccap + u];
   __syncthreads();
   for (int u = lane; u < n_c; u += 64) {
-    const int32_t e = s_raw[u];
+    const int32_t e = L.raw[u];
     int r = 0;
-    for (int w = 0; w < n_c; ++w) r += (s_raw[w] < e);
+    for (int w = 0; w < n_c; ++w) r += (L.raw[w] < e);
     const double4 q = s.pos[e];
-    s_center[r] = e;
-    s_base[r] = 0;
-    s_cx[r] = q.x;
-    s_cy[r] = q.y;
-    s_cz[r] = q.z;
+    L.center[r] = e;
+    L.base[r] = 0;
+    L.cx[r] = q.x;
+    L.cy[r] = q.y;
+    L.cz[r] = q.z;
   }
   __syncthreads();
   const double Lx = rp.box[0], Ly = rp.box[1], Lz = rp.box[2];
@@ -338,28 +363,33 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
   const int32_t cap = g.nbr_cap;
   int s0 = 0;
   while (s0 < 27) {
+    // the largest run of stencil cells whose candidates fit the stage (one
+    // cell always fits: the capacity is at most kMaxStage)
     int s1 = s0 + 1;
-    while (s1 < 27 && s_off[s1 + 1] - s_off[s0] <= kMaxStage) ++s1;
-    const int base_off = s_off[s0];
-    const int T = s_off[s1] - base_off;
-    for (int p = lane; p < T; p += 64) {
-      const int gs = base_off + p;
-      int sc = s0;
-      while (s_off[sc + 1] <= gs) ++sc;
-      s_raw[p] = s.bin_idx[(int64_t)s_q[sc] * ccap + (gs - s_off[sc])];
-      s_cell[p] = (int8_t)sc;
+    while (s1 < 27 && L.off[s1 + 1] - L.off[s0] <= kMaxStage) ++s1;
+    const int base_off = L.off[s0];
+    const int T = L.off[s1] - base_off;
+    // each stencil cell's lane marks its slots, then every lane loads its slots
+    if (lane >= s0 && lane < s1) {
+      const int lo = L.off[lane] - base_off;
+      for (int w = 0; w < n; ++w) L.cell[lo + w] = (int8_t)lane;
     }
     __syncthreads();
     for (int p = lane; p < T; p += 64) {
-      const int sc = s_cell[p];
-      const int lo = s_off[sc] - base_off, n = s_n[sc];
-      const int32_t e = s_raw[p];
+      const int sc = L.cell[p];
+      L.raw[p] = s.bin_idx[(int64_t)L.q[sc] * ccap + (p + base_off - L.off[sc])];
+    }
+    __syncthreads();
+    for (int p = lane; p < T; p += 64) {
+      const int sc = L.cell[p];
+      const int lo = L.off[sc] - base_off, nn = L.n[sc];
+      const int32_t e = L.raw[p];
       int r = 0;
-      for (int w = lo; w < lo + n; ++w) r += (s_raw[w] < e);
-      s_idx[lo + r] = e;
+      for (int w = lo; w < lo + nn; ++w) r += (L.raw[w] < e);
+      L.idx[lo + r] = e;
     }
     __syncthreads();
-    // candidates into registers (s_cell is per stencil cell, unchanged by the sort)
+    // candidates into registers (L.cell is per stencil cell, unchanged by the sort)
     double px[kBuildChunks], py[kBuildChunks], pz[kBuildChunks];
     double sx[kBuildChunks], sy[kBuildChunks], sz[kBuildChunks];
     uint32_t ent[kBuildChunks];
@@ -371,8 +401,8 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
       sx[k] = sy[k] = sz[k] = 0.0;
       ent[k] = 0xffffffffu;
       if (p < T) {
-        const int32_t j = s_idx[p];
-        const uint32_t code = (uint32_t)s_code[s_cell[p]];
+        const int32_t j = L.idx[p];
+        const uint32_t code = (uint32_t)L.code[L.cell[p]];
         const double4 q = s.pos[j];
         px[k] = q.x;
         py[k] = q.y;
@@ -384,10 +414,10 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
       }
     }
     for (int u = 0; u < n_c; ++u) {
-      const int32_t i = s_center[u];
+      const int32_t i = L.center[u];
       const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
-      const double qx = s_cx[u], qy = s_cy[u], qz = s_cz[u];
-      int base = s_base[u];
+      const double qx = L.cx[u], qy = L.cy[u], qz = L.cz[u];
+      int base = L.base[u];
 #pragma unroll
       for (int k = 0; k < kBuildChunks; ++k) {
         if (k * 64 >= T) break;
@@ -406,7 +436,7 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
         }
         base += __popcll(m);
       }
-      if (lane == 0) s_base[u] = base;
+      if (lane == 0) L.base[u] = base;
     }
     __syncthreads();
     s0 = s1;
@@ -414,8 +444,8 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
   int32_t mx = 0;
   long long tot = 0;
   for (int u = lane; u < n_c; u += 64) {
-    const int32_t b = s_base[u];
-    s.cnt[s_center[u]] = b;
+    const int32_t b = L.base[u];
+    s.cnt[L.center[u]] = b;
     mx = max(mx, b);
     tot += b;
   }
@@ -441,7 +471,8 @@ __global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t
   const int32_t due = cond ? *cond : 1;
   const bool err = has_error(s.status);
   if (due == 0 || err) return;
-  __shared__ BuildLds lds;
+  extern __shared__ double build_lds_raw[];
+  const BuildLds lds = carve_build_lds(reinterpret_cast<char*>(build_lds_raw), g.cell_cap);
   for (int b = blockIdx.x; b < g.n_ctiles; b += gridDim.x) {
     const CellTile ct = g.ctiles[b];
     if (ct.cell < 0) continue;
@@ -1093,8 +1124,9 @@ hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const 
 
 hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                         const int32_t* rcond) {
-  const int grid = std::min(L.ctile_blocks, 12 * L.persist_blocks);
-  hipLaunchKernelGGL(k_build, dim3(grid), dim3(kBuildBlock), 0, L.stream, g, s, cond, rcond);
+  const int grid = std::min(L.ctile_blocks, 24 * L.persist_blocks);
+  hipLaunchKernelGGL(k_build, dim3(grid), dim3(kBuildBlock), build_lds_bytes(g.cell_cap),
+                     L.stream, g, s, cond, rcond);
   return hipGetLastError();
 }
 
