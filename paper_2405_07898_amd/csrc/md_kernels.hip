@@ -633,9 +633,24 @@ __device__ __forceinline__ TileWalk tile_walk() {
   return w;
 }
 
-template <class T>
-__device__ __forceinline__ void lds_fill(T* dst, const T* __restrict__ src, int n) {
-  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+// Table rows into LDS: each thread requests all its rows of a round (kU of
+// them) before storing any, so a round costs one memory latency, not one per
+// row.  Nothing branches: indexes past the end load the last row again and
+// store into a junk row of the lane (a branch around each load or store makes
+// the compiler wait for every load before the next).
+constexpr size_t kLdsJunkBytes = 64 * sizeof(double4);
+
+template <int kU, class T>
+__device__ __forceinline__ void lds_fill(T* dst, const T* __restrict__ src, int n, void* junk) {
+  const int nt = (int)blockDim.x;
+  T* const jr = reinterpret_cast<T*>(junk) + (threadIdx.x & 63);
+  for (int b = (int)threadIdx.x; b < n; b += kU * nt) {
+    T v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = src[min(b + u * nt, n - 1)];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) *(b + u * nt < n ? dst + b + u * nt : jr) = v[u];
+  }
 }
 
 __device__ __forceinline__ void separation(uint32_t e, const RepDev& rp, double qx, double qy,
@@ -739,19 +754,25 @@ __global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
                                                   const int32_t* cond_zero, int32_t* clear_flag,
                                                   int32_t* rclear, int64_t ncells, int want_rho) {
   extern __shared__ double4 lds_d4[];
+  // both control words are read before either is used (one memory latency),
+  // and the table is loaded while they arrive; the error test is uniform
+  const int32_t zero_bins = cond_zero ? *cond_zero : 0;
+  const bool err = has_error(s.status);
   if (clear_flag && blockIdx.x == 0) {
     if (threadIdx.x == 0) *clear_flag = 0;
     for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rclear[r] = 0;
   }
-  if (cond_zero && *cond_zero) {
+  if (PREC == 0) lds_fill<4>(lds_d4, t.rho_val, t.nr - 1, lds_d4 + (t.nr - 1));
+  else
+    lds_fill<4>(reinterpret_cast<float4*>(lds_d4), t.rho_val32, t.nr - 1,
+                reinterpret_cast<float4*>(lds_d4) + (t.nr - 1));
+  if (zero_bins) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncells;
          k += (int64_t)gridDim.x * blockDim.x)
       s.bin_cnt[k] = 0;
   }
-  if (has_error(s.status)) return;
-  if (PREC == 0) lds_fill(lds_d4, t.rho_val, t.nr - 1);
-  else lds_fill(reinterpret_cast<float4*>(lds_d4), t.rho_val32, t.nr - 1);
   __syncthreads();
+  if (err) return;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
     const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
@@ -869,11 +890,13 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
 template <int PREC>
 __device__ __forceinline__ void fill_force_table(void* lds, const Tables& t) {
   if (PREC == 0) {
-    lds_fill(reinterpret_cast<double2*>(lds), t.dpair3, 3 * (t.nr - 1));
+    double2* d = reinterpret_cast<double2*>(lds);
+    lds_fill<8>(d, t.dpair3, 3 * (t.nr - 1), d + 3 * (t.nr - 1));
   } else {
     float4* ta = reinterpret_cast<float4*>(lds);
-    lds_fill(ta, t.dpair_a32, t.nr - 1);
-    lds_fill(reinterpret_cast<float2*>(ta + (t.nr - 1)), t.dpair_b32, t.nr - 1);
+    float2* tb = reinterpret_cast<float2*>(ta + (t.nr - 1));
+    lds_fill<2>(ta, t.dpair_a32, t.nr - 1, tb + (t.nr - 1));
+    lds_fill<2>(tb, t.dpair_b32, t.nr - 1, tb + (t.nr - 1));
   }
 }
 
@@ -886,10 +909,12 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
     Geometry g, State s, Tables t, const double4* __restrict__ pos_in,
     double4* __restrict__ pos_out, int32_t* flag_next, int32_t* rflag_next) {
   extern __shared__ double4 lds_d4[];
-  if (has_error(s.status)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
+  // the status word arrives while the table loads (the test is uniform)
+  const bool err = has_error(s.status);
   fill_force_table<PREC>(lds_d4, t);
   __syncthreads();
+  if (err) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
     const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
@@ -940,9 +965,10 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry 
                                                                         Tables t,
                                                                         const double4* __restrict__ pos) {
   extern __shared__ double4 lds_d4[];
-  if (has_error(s.status)) return;
+  const bool err = has_error(s.status);
   fill_force_table<PREC>(lds_d4, t);
   __syncthreads();
+  if (err) return;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
     const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
@@ -1153,12 +1179,14 @@ static int pair_threads(int prec, bool force, int lpa) {
   return 64 * lpa * tpi;
 }
 
+// table rows plus the junk rows of the fill
 size_t density_lds_bytes(const Tables& t, int prec) {
-  return (size_t)(t.nr - 1) * (prec == 0 ? sizeof(double4) : sizeof(float4));
+  return (size_t)(t.nr - 1) * (prec == 0 ? sizeof(double4) : sizeof(float4)) + kLdsJunkBytes;
 }
 
 size_t force_lds_bytes(const Tables& t, int prec) {
-  return (size_t)(t.nr - 1) * (prec == 0 ? 3 * sizeof(double2) : sizeof(float4) + sizeof(float2));
+  return (size_t)(t.nr - 1) * (prec == 0 ? 3 * sizeof(double2) : sizeof(float4) + sizeof(float2)) +
+         kLdsJunkBytes;
 }
 
 template <int PREC, int LPA>
