@@ -1,0 +1,98 @@
+"""Parity at the benchmark's full sizes, in the benchmark's launch configuration.
+
+The 128,000-atom and 802,344-atom boxes are built with the same parameters as
+bench.py (hipGraph chunks of 100 steps, list capacity 128, cell capacity 64,
+lanes per atom from the autotuner).  Against the FP64 oracle:
+- cell ids of every atom and list lengths of every atom: bit-exact;
+- neighbour sets: bit-exact on a seeded sample of 4,096 atoms;
+- rho_i, F'(rho_i): 1e-12 relative; forces: 1e-10 relative (max-norm over
+  atoms, relative to the largest force); potential energy: 1e-12 relative;
+- after 100 graph-captured steps: positions within 1e-9 A, velocities within
+  1e-11 A/fs of the oracle's velocity-Verlet run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+from workloads import configs, potential as P
+
+pytestmark = pytest.mark.gpu
+
+RC, SKIN = P.RC, configs.SKIN
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2405_07898_amd import md as mdmod
+
+    mdmod.lib()
+    return mdmod
+
+
+@pytest.fixture(scope="module")
+def tabs():
+    return P.md_tables()
+
+
+SIZES = [("128k", configs.config_128k), ("810k", configs.config_810k)]
+
+
+@pytest.mark.parametrize("name,make", SIZES, ids=[s[0] for s in SIZES])
+def test_full_size_cells_lists_forces(md, tabs, oracle_lib, name, make):
+    box = make()
+    _say(f"[gpu] full size {name}: n={box.n} cells/lists/forces")
+    s = bench.make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    lpa, _ = s.autotune(5)
+    _say(f"[gpu]   lanes per atom {lpa}")
+    cell_g = s.cells().cpu().numpy()
+    cell_o, _, _ = oracle_lib.cell_ids(box.x, box.box, RC + SKIN)
+    assert np.array_equal(cell_g, cell_o)
+    cnt_g, nbr_g = s.neighbors(128)
+    cnt_g, nbr_g = cnt_g.cpu().numpy(), nbr_g.cpu().numpy()
+    cnt_o, nbr_o, _ = oracle_lib.neighbor_list(box.x, box.box, RC + SKIN, cap=128)
+    assert np.array_equal(cnt_g, cnt_o)
+    pick = np.sort(np.random.default_rng(7).choice(box.n, 4096, replace=False))
+    for i in pick:
+        assert set(nbr_g[i, :cnt_g[i]].tolist()) == set(nbr_o[i, :cnt_o[i]].tolist()), i
+    f, rho, fp = s.compute_forces()
+    ref = oracle_lib.forces_at(box.x, box.box, tabs, RC, SKIN)
+    assert _rel(rho.cpu().numpy(), ref["rho"]) < 1e-12
+    assert _rel(fp.cpu().numpy(), ref["fp"]) < 1e-12
+    assert _rel(f.cpu().numpy(), ref["f"]) < 1e-10
+    pe, _ = s.energy()
+    assert abs(pe[0] - ref["pe"]) <= 1e-12 * abs(ref["pe"])
+    s.close()
+
+
+@pytest.mark.parametrize("name,make", SIZES, ids=[s[0] for s in SIZES])
+def test_full_size_trajectory_100_steps(md, tabs, oracle_lib, name, make):
+    box = make()
+    _say(f"[gpu] full size {name}: n={box.n} 100 graph steps")
+    s = bench.make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    s.autotune(5)
+    s.step(100)
+    x, v, _ = s.get_state()
+    st = s.stats()
+    s.close()
+    out = oracle_lib.md_run(box.x, box.v, box.box, tabs, 100, mass=configs.MASS, dt=configs.DT,
+                            r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+    assert out["code"] == 0
+    d = x.cpu().numpy() - out["x"]
+    d -= box.box * np.round(d / box.box)
+    assert np.max(np.abs(d)) < 1e-9
+    assert np.max(np.abs(v.cpu().numpy() - out["v"])) < 1e-11
+    assert st["steps"] == 100
