@@ -465,8 +465,11 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
 
 // Launched with a grid smaller than the cell count (workgroup b takes cell
 // tiles b, b + G, ...; G is a multiple of the XCD count, so every tile stays on
-// the XCD the tile table placed it on).
-__global__ __launch_bounds__(64) void k_build(Geometry g, State s, const int32_t* cond,
+// the XCD the tile table placed it on).  The register budget asks for six
+// waves per SIMD: the build is latency-bound, and the few spilled registers
+// cost less than the lost occupancy (measured: 330 us against 435 us at
+// 802k atoms).
+__global__ __launch_bounds__(64, 6) void k_build(Geometry g, State s, const int32_t* cond,
                                               const int32_t* rcond) {
   const int32_t due = cond ? *cond : 1;
   const bool err = has_error(s.status);
