@@ -1146,7 +1146,7 @@ hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_tot
 
 hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                       const int32_t* rcond) {
-  const int grid = std::min(L.atile_blocks, 4 * L.persist_blocks);
+  const int grid = std::min(L.atile_blocks, 16 * L.persist_blocks);
   hipLaunchKernelGGL(k_bin, dim3(grid), dim3(64), 0, L.stream, g, s, cond, rcond);
   return hipGetLastError();
 }
