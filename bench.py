@@ -170,6 +170,25 @@ def bench_small(torch, md, configs, tabs):
             "rebuilds": st["rebuilds"]}
 
 
+def bench_stable(torch, md, configs, potential, steps):
+    """Context only, not the specified workload: the 128,000-atom box with the
+    STABLE parameter set (a solid at 300 K, rebuilds about every 50 steps)."""
+    box = configs.config_128k()
+    tabs = potential.md_tables(p=potential.STABLE)
+    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    lpa, _ = s.autotune(50)
+    s.step(100)
+    st0 = s.stats()
+    sec, _ = time_steps(torch, s, steps)
+    st1 = s.stats()
+    s.close()
+    return {"potential": "STABLE (context only; not the benchmark's potential)",
+            "n_atoms": box.n, "steps": steps, "lanes_per_atom": lpa,
+            "timesteps_per_s": round(steps / sec, 1),
+            "rebuilds": int(st1["rebuilds"] - st0["rebuilds"]),
+            "mean_list_length": round(st1["list_entries"] / box.n, 3)}
+
+
 def bench_batched(torch, md, configs, tabs, args):
     """256 replicas (5-20 cells, 0-2 % vacancies, 300-2000 K) in one launch per pass,
     against a sequential loop of single-replica contexts."""
@@ -381,6 +400,8 @@ def main() -> int:
                                  "workload": "74^3 BCC sites - 1% vacancies, 2500 K", **sec_out}
 
     if not args.no_secondary:
+        out["secondary_stable_128k"] = bench_stable(torch, md, configs, potential, 5000)
+        log(f"  stable-lattice context: {out['secondary_stable_128k']}")
         out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)
         log(f"  small: {out['secondary_small_2000']}")
         out["secondary_batched_256"] = bench_batched(torch, md, configs, tabs, args)

@@ -5,19 +5,19 @@ CPU oracle and the GPU library receive as data (the paper lets rho, F and phi be
 arbitrary polynomial splines, Sec. II-A, after Eq. (potential)).  Nothing here
 evaluates the EAM energy or forces of a configuration.
 
-Analytic forms (units: Angstrom, eV):
+Analytic forms (units: Angstrom, eV), the benchmark's specified potential:
     fc(r)   = (1 - (r/rc)^2)^3            for r < rc, else 0
-    phi(r)  = (A exp(-8 (r/r0 - 1)) - W exp(-((r - a)/s)^2)) * fc(r)
+    phi(r)  = 0.3 * exp(-8 (r/r0 - 1)) * fc(r)
     rho(r)  = exp(-6 (r/r0 - 1)) * fc(r)
-    F(rho)  = -3 * sqrt(rho)
-with rc = 5.0, r0 = 2.86 (the first-neighbour distance of BCC at a = 3.304),
-A = 1.5514, and a shallow well W = 0.14 eV, s = 0.2 A centred on the
-second-neighbour distance a.  A sets zero pressure for BCC at a = 3.304; the
-well makes the tetragonal shear modulus positive (without it the BCC lattice
-shears towards close packing and the crystal collapses and heats).  Per-atom
-lattice-sum curvatures at a = 3.304 (eV per unit linear strain squared):
-hydrostatic 197.5, tetragonal 72.6, monoclinic 22.7; a solid at 300 K keeps
-its 26 neighbours inside rc.
+    F(rho)  = -2 * sqrt(rho)
+with rc = 5.0 and r0 = 2.86.  This BCC lattice at a = 3.304 is far from zero
+pressure and unstable under tetragonal shear, so MD boxes collapse and heat
+(hot, dense, frequent list rebuilds).
+
+STABLE is a second parameter set, used only for a labelled extra benchmark
+point: phi gets amplitude 1.5514 (zero pressure at a = 3.304) plus a shallow
+well -0.14 exp(-((r - 3.304)/0.2)^2) at the second-neighbour distance (positive
+shear modulus), and F = -3 sqrt(rho); its crystal stays solid at 300 K.
 
 Table layout (shared convention of both consumers): a spline with n knots on
 [x0, x0 + (n-1)*dx] stores, for every segment k in [0, n-2], four coefficients
@@ -34,13 +34,13 @@ from scipy.interpolate import CubicSpline
 
 RC = 5.0
 R0 = 2.86
-PHI_A = 1.5514
+PHI_A = 0.3
 PHI_B = 8.0
-WELL_W = 0.14
+WELL_W = 0.0
 WELL_S = 0.2
 WELL_R = 3.304
 RHO_B = 6.0
-EMB_A = 3.0
+EMB_A = 2.0
 RHO_MAX = 40.0
 N_KNOTS_MD = 2000
 
@@ -66,10 +66,14 @@ class SplineTable:
         return self.x0 + (self.n_knots - 1) * self.dx
 
 
-def analytic_params() -> dict:
-    """The constants above, for evaluators of the closed forms."""
-    return dict(rc=RC, r0=R0, phi_a=PHI_A, phi_b=PHI_B, rho_b=RHO_B, emb_a=EMB_A,
-                well_w=WELL_W, well_s=WELL_S, well_r=WELL_R)
+SPEC = dict(phi_a=PHI_A, well_w=WELL_W, emb_a=EMB_A)
+STABLE = dict(phi_a=1.5514, well_w=0.14, emb_a=3.0)
+
+
+def analytic_params(p: dict = SPEC) -> dict:
+    """All constants of a parameter set, for evaluators of the closed forms."""
+    return dict(rc=RC, r0=R0, phi_a=p["phi_a"], phi_b=PHI_B, rho_b=RHO_B, emb_a=p["emb_a"],
+                well_w=p["well_w"], well_s=WELL_S, well_r=WELL_R)
 
 
 # --- analytic functions (vectorised numpy) ---------------------------------
@@ -86,45 +90,46 @@ def dfc(r):
     return np.where(r < RC, 3.0 * u ** 2 * (-2.0 * r / RC ** 2), 0.0)
 
 
-def _pair_core(r):
+def _pair_core(r, p):
     r = np.asarray(r, dtype=np.float64)
-    return PHI_A * np.exp(-PHI_B * (r / R0 - 1.0)) - WELL_W * np.exp(-((r - WELL_R) / WELL_S) ** 2)
+    return (p["phi_a"] * np.exp(-PHI_B * (r / R0 - 1.0))
+            - p["well_w"] * np.exp(-((r - WELL_R) / WELL_S) ** 2))
 
 
-def _dpair_core(r):
+def _dpair_core(r, p):
     r = np.asarray(r, dtype=np.float64)
     u = (r - WELL_R) / WELL_S
-    return (PHI_A * (-PHI_B / R0) * np.exp(-PHI_B * (r / R0 - 1.0))
-            + WELL_W * (2.0 * u / WELL_S) * np.exp(-u ** 2))
+    return (p["phi_a"] * (-PHI_B / R0) * np.exp(-PHI_B * (r / R0 - 1.0))
+            + p["well_w"] * (2.0 * u / WELL_S) * np.exp(-u ** 2))
 
 
-def phi(r):
-    return _pair_core(r) * fc(r)
+def phi(r, p=SPEC):
+    return _pair_core(r, p) * fc(r)
 
 
-def dphi(r):
-    return _dpair_core(r) * fc(r) + _pair_core(r) * dfc(r)
+def dphi(r, p=SPEC):
+    return _dpair_core(r, p) * fc(r) + _pair_core(r, p) * dfc(r)
 
 
-def rho(r):
+def rho(r, p=SPEC):
     return np.exp(-RHO_B * (np.asarray(r) / R0 - 1.0)) * fc(r)
 
 
-def drho(r):
+def drho(r, p=SPEC):
     e = np.exp(-RHO_B * (np.asarray(r) / R0 - 1.0))
     return e * (-RHO_B / R0) * fc(r) + e * dfc(r)
 
 
-def emb(p):
-    return -EMB_A * np.sqrt(np.asarray(p, dtype=np.float64))
+def emb(x, p=SPEC):
+    return -p["emb_a"] * np.sqrt(np.asarray(x, dtype=np.float64))
 
 
-def demb(p):
-    return -0.5 * EMB_A / np.sqrt(np.asarray(p, dtype=np.float64))
+def demb(x, p=SPEC):
+    return -0.5 * p["emb_a"] / np.sqrt(np.asarray(x, dtype=np.float64))
 
 
-def ddemb(p):
-    return 0.25 * EMB_A * np.asarray(p, dtype=np.float64) ** -1.5
+def ddemb(x, p=SPEC):
+    return 0.25 * p["emb_a"] * np.asarray(x, dtype=np.float64) ** -1.5
 
 
 # --- tabulation ---------------------------------------------------------------
@@ -150,9 +155,10 @@ def tabulate(fn, x1: float, n_knots: int) -> SplineTable:
     return natural_spline_from_values(0.0, dx, fn(xs))
 
 
-def md_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX):
+def md_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX, p: dict = SPEC):
     """(phi, rho, F) tables used by every MD workload: phi, rho on [0, rc], F on [0, rho_max]."""
-    return tabulate(phi, RC, n_knots), tabulate(rho, RC, n_knots), tabulate(emb, rho_max, n_knots)
+    return (tabulate(lambda r: phi(r, p), RC, n_knots), tabulate(lambda r: rho(r, p), RC, n_knots),
+            tabulate(lambda x: emb(x, p), rho_max, n_knots))
 
 
 def spline_value_map(n_knots: int) -> np.ndarray:
