@@ -89,7 +89,12 @@ int32_t or_get_threads(void) {
 /* ------------------------------------------------------------------ splines */
 
 /* Segment of a per-segment cubic table: x = alpha (s - x0), k = int(x) clamped
- * to [0, n-2], t = x - k (beyond the last knot t > 1 extrapolates the last cubic). */
+ * to [0, n-2], t = x - k.  Past the last knot (t > 1 on the last segment) the
+ * function continues as the straight line tangent at that knot: value
+ * f(1) + f_t(1) (t - 1), slope f_t(1), curvature 0.  (Reading: the paper does
+ * not say what a table does outside its range; the last cubic itself, taken
+ * far outside its interval, grows like t^3, and for F it turns a dense
+ * cluster at rho > rho_max into a runaway.) */
 static void seg_of(const or_spline *sp, double s, int *k, double *t) {
   double x = (s - sp->x0) * sp->inv_dx;
   int last = sp->n_knots - 2;
@@ -106,6 +111,7 @@ static double spl_f(const or_spline *sp, double s) {
   double t;
   seg_of(sp, s, &k, &t);
   const double *c = sp->coef + 4 * (size_t)k;
+  if (t > 1.0) return (c[0] + c[1] + c[2] + c[3]) + (c[1] + 2.0 * c[2] + 3.0 * c[3]) * (t - 1.0);
   return c[0] + t * (c[1] + t * (c[2] + t * c[3]));
 }
 
@@ -113,6 +119,7 @@ static double spl_df(const or_spline *sp, double s) {
   int k;
   double t;
   seg_of(sp, s, &k, &t);
+  if (t > 1.0) t = 1.0;
   const double *c = sp->coef + 4 * (size_t)k;
   return (c[1] + t * (2.0 * c[2] + t * (3.0 * c[3]))) * sp->inv_dx;
 }
@@ -121,6 +128,7 @@ static double spl_ddf(const or_spline *sp, double s) {
   int k;
   double t;
   seg_of(sp, s, &k, &t);
+  if (t > 1.0) return 0.0;
   const double *c = sp->coef + 4 * (size_t)k;
   return (2.0 * c[2] + 6.0 * c[3] * t) * sp->inv_dx * sp->inv_dx;
 }
@@ -715,6 +723,7 @@ double or_fm_loss_grad(int32_t n_cfg, const int64_t *off, const double *x, const
           int ke;
           double te;
           seg_of(emb, rh[i], &ke, &te);
+          if (te > 1.0) te = 1.0; /* tangent-line continuation past the last knot */
           gem[4 * ke + 1] += lam[i] * emb->inv_dx;
           gem[4 * ke + 2] += lam[i] * 2.0 * te * emb->inv_dx;
           gem[4 * ke + 3] += lam[i] * 3.0 * te * te * emb->inv_dx;

@@ -72,11 +72,13 @@ __device__ __forceinline__ void seg(const FmSpline& sp, double v, int& k, double
   t = x - (double)k;
 }
 
+// Past the last knot (t > 1) a table continues along its end tangent.
 __device__ __forceinline__ double sp_f(const FmSpline& sp, double v) {
   int k;
   double t;
   seg(sp, v, k, t);
   const double* c = sp.coef + 4 * k;
+  if (t > 1.0) return (c[0] + c[1] + c[2] + c[3]) + (c[1] + 2.0 * c[2] + 3.0 * c[3]) * (t - 1.0);
   return c[0] + t * (c[1] + t * (c[2] + t * c[3]));
 }
 
@@ -84,6 +86,7 @@ __device__ __forceinline__ double sp_df(const FmSpline& sp, double v) {
   int k;
   double t;
   seg(sp, v, k, t);
+  t = fmin(t, 1.0);
   const double* c = sp.coef + 4 * k;
   return (c[1] + t * (2.0 * c[2] + t * (3.0 * c[3]))) * sp.inv_dx;
 }
@@ -92,6 +95,7 @@ __device__ __forceinline__ double sp_ddf(const FmSpline& sp, double v) {
   int k;
   double t;
   seg(sp, v, k, t);
+  if (t > 1.0) return 0.0;
   const double* c = sp.coef + 4 * k;
   return (2.0 * c[2] + 6.0 * c[3] * t) * sp.inv_dx * sp.inv_dx;
 }
@@ -213,14 +217,12 @@ __global__ __launch_bounds__(64) void k_fm_lambda(FmArgs a) {
     const double mu = acc * a.fpp[i];
     a.lam[i] = acc;
     a.mu[i] = mu;
-    // |w| <= |g_i|; factors m t^(m-1) <= 3 (t <= 1 inside the table; a
-    // density past the F table gives t > 1, covered by the te^2 factor)
+    // |w| <= |g_i|; factors m t^(m-1) <= 3 (t <= 1, also past the F table,
+    // where F continues along its end tangent)
     const double gn = sqrt((gi.x * gi.x + gi.y * gi.y) + gi.z * gi.z);
     const double a_pr = 3.0 * fmax(a.phi.inv_dx, a.rho.inv_dx);
-    const double xe = (a.rho_i[i] - a.emb.x0) * a.emb.inv_dx;
-    const double te = fmax(1.0, xe - (double)(a.emb.n - 2));
     bnd = fmax(gn * a_pr * (1.0 + fabs(a.fp[i]) + fpmax) + fabs(mu),
-               fabs(acc) * 3.0 * a.emb.inv_dx * te * te);
+               fabs(acc) * 3.0 * a.emb.inv_dx);
     if (!isfinite(bnd)) bnd = HUGE_VAL;
   }
   s_b[threadIdx.x] = bnd;
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(64) void k_fm_coef(FmArgs a) {
     int ke;
     double te;
     seg(a.emb, a.rho_i[i], ke, te);
+    te = fmin(te, 1.0);  // end tangent past the last knot
     const double li = a.lam[i], ae = a.emb.inv_dx;
     fix_add(he, 4 * ke + 1, li * ae, S, a.flag);
     fix_add(he, 4 * ke + 2, li * 2.0 * te * ae, S, a.flag);

@@ -790,7 +790,8 @@ __global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
     const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
     const int le = t.ne - 2;
     const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
-    const double te = xe - (double)ke;
+    // past the last knot F continues along its end tangent: F' = F'(end)
+    const double te = fmin(xe - (double)ke, 1.0);
     const double4 ce = t.emb_val[ke];
     double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
     if (PREC != 0) fp = (double)(float)fp;
@@ -1044,7 +1045,11 @@ __global__ __launch_bounds__(64) void k_energy_atoms(Geometry g, State s, Tables
     const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
     const double te = xe - (double)ke;
     const double4 c = t.emb_val[ke];
-    ep = 0.5 * ph + fma(fma(fma(c.w, te, c.z), te, c.y), te, c.x);
+    // past the last knot F continues along its end tangent
+    const double fe = (te > 1.0) ? ((c.x + c.y + c.z + c.w) +
+                                    (c.y + 2.0 * c.z + 3.0 * c.w) * (te - 1.0))
+                                 : fma(fma(fma(c.w, te, c.z), te, c.y), te, c.x);
+    ep = 0.5 * ph + fe;
     const double4 v = s.vel[i];
     const double4 f = s.frc[i];
     const double ux = fma(vscale, f.x, v.x), uy = fma(vscale, f.y, v.y), uz = fma(vscale, f.z, v.z);

@@ -162,6 +162,24 @@ def test_lanes_per_atom_agree(md, tabs):
         assert _rel(f, fs[0]) < 1e-13
 
 
+def test_density_past_the_f_table(md, tabs, oracle_lib):
+    """A compressed lattice (a = 2.2 A) puts every rho_i above the F table's
+    end (40): F' comes from the end tangent on both sides, and the library
+    reports the range warning."""
+    box = configs.small_box(8, seed=55, a=2.2, sigma_x=0.02)
+    _say(f"[gpu] density past the F table n={box.n}")
+    s = _system(md, tabs, box)
+    s.build_neighbors()
+    f, rho, fp = s.compute_forces()
+    ref = oracle_lib.forces_at(box.x, box.box, tabs, RC, SKIN, cap=256)
+    assert ref["rho"].min() > tabs[2].x1
+    assert _rel(rho.cpu().numpy(), ref["rho"]) < 1e-12
+    assert _rel(fp.cpu().numpy(), ref["fp"]) < 1e-12
+    assert _rel(f.cpu().numpy(), ref["f"]) < 1e-10
+    assert s.stats()["status_bits"] & 256
+    s.close()
+
+
 def test_error_paths(md, tabs):
     box = configs.small_box(6, seed=53)
     _say("[gpu] error paths")

@@ -59,6 +59,22 @@ def test_spline_tables_match_analytic(oracle_lib, md_tables):
     assert np.max(np.abs(dd - P.ddemb(p))[p > 1.0]) < m_end + 3.0 / 8.0 * h ** 2 * f4(1.0)
 
 
+def test_table_continues_along_end_tangent(oracle_lib, md_tables):
+    """Past the last knot a table is the straight line tangent at that knot:
+    value and slope continuous at the end, slope constant and curvature zero
+    beyond (the reading for densities above the F table, e.g. a compressed
+    cluster at rho > 40)."""
+    _, _, emb_t = md_tables
+    end = emb_t.x1
+    e = 1e-7
+    v0, d0, _ = oracle_lib.spline_eval(emb_t, np.array([end - e, end]))
+    assert abs(v0[1] - v0[0] - d0[1] * e) < 1e-12 and abs(d0[1] - d0[0]) < 1e-9
+    x = end + np.array([0.5, 3.0, 17.0, 260.0])
+    v, d, dd = oracle_lib.spline_eval(emb_t, x)
+    assert np.all(d == d0[1]) and np.all(dd == 0.0)
+    np.testing.assert_allclose(v, v0[1] + d0[1] * (x - end), rtol=1e-14, atol=1e-12)
+
+
 def test_spline_knots_interpolate(oracle_lib, md_tables):
     """At the knots the tables return the sampled analytic values to rounding."""
     phi_t, _, _ = md_tables
