@@ -191,6 +191,55 @@ def bench_stable(torch, md, configs, potential, steps):
             "mean_list_length": round(st1["list_entries"] / box.n, 3)}
 
 
+def perf_model(torch, md, configs, tabs, steps: int = 1000):
+    """Linear model of the step time at fixed N, t = A n_l + B n_int + C (the
+    paper's Eq. linearmodel / Table "regression", with list entries standing
+    in for candidates): dt = 0 sweeps over the interaction cutoff and the skin
+    on the 128,000-atom lattice, so the list never changes."""
+    from workloads import potential
+
+    box = configs.config_128k()
+    rows = []
+    for rc in (3.0, 3.5, 4.0, 5.0):
+        for skin in (0.3, 0.8, 1.4, 2.2):
+            p = md.make_params(mass=configs.MASS, dt=0.0, r_cut=rc, skin=skin,
+                               ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
+                               lanes_per_atom=2, nbr_capacity=160, cell_capacity=64,
+                               sort_every=0)
+            s = md.System(p, tabs, [box.n], box.box[None, :])
+            s.set_state(box.x, box.v)
+            s.build_neighbors()
+            s.step(200)
+            sec, _ = time_steps(torch, s, steps)
+            n_l = s.stats()["list_entries"] / box.n
+            cnt, nbr = s.neighbors(160)
+            s.close()
+            # interactions (r < r_cut) of a fixed sample of atoms, from the exported list
+            pick = np.random.default_rng(9).choice(box.n, 4096, replace=False)
+            c = cnt.cpu().numpy()[pick]
+            nb = nbr.cpu().numpy()[pick]
+            n_int = 0
+            for a, ca, na in zip(pick, c, nb):
+                d = box.x[na[:ca]] - box.x[a]
+                d -= box.box * np.round(d / box.box)
+                n_int += int(np.count_nonzero((d * d).sum(1) < rc * rc))
+            rows.append((n_l, n_int / len(pick), sec / steps * 1e6, rc, skin))
+    m = np.array(rows)
+    X = np.column_stack([m[:, 0], m[:, 1], np.ones(len(m))])
+    coef, *_ = np.linalg.lstsq(X, m[:, 2], rcond=None)
+    pred = X @ coef
+    r2 = 1.0 - np.sum((m[:, 2] - pred) ** 2) / np.sum((m[:, 2] - m[:, 2].mean()) ** 2)
+    return {"n_atoms": box.n, "steps_per_point": steps, "lanes_per_atom": 2,
+            "us_per_step_per_list_entry": round(float(coef[0]), 4),
+            "us_per_step_per_interaction": round(float(coef[1]), 4),
+            "us_per_step_fixed": round(float(coef[2]), 3),
+            "ns_per_atom_list_entry": round(float(coef[0]) * 1e3 / box.n, 6),
+            "ns_per_atom_interaction": round(float(coef[1]) * 1e3 / box.n, 6),
+            "r2": round(float(r2), 5),
+            "points": [{"r_cut": r[3], "skin": r[4], "n_l": round(r[0], 3),
+                        "n_int": round(r[1], 3), "us_per_step": round(r[2], 3)} for r in rows]}
+
+
 def bench_batched(torch, md, configs, tabs, args):
     """256 replicas (5-20 cells, 0-2 % vacancies, 300-2000 K) in one launch per pass,
     against a sequential loop of single-replica contexts."""
@@ -405,6 +454,11 @@ def main() -> int:
         out["secondary_stable_128k"] = bench_stable(torch, md, configs, potential, 5000)
         log(f"  stable-lattice context: {out['secondary_stable_128k']}")
         out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)
+        out["secondary_perf_model"] = perf_model(torch, md, configs, tabs)
+        pm = out["secondary_perf_model"]
+        log(f"  perf model: t = {pm['us_per_step_per_list_entry']} n_l + "
+            f"{pm['us_per_step_per_interaction']} n_int + {pm['us_per_step_fixed']} us, "
+            f"r2 {pm['r2']}")
         log(f"  small: {out['secondary_small_2000']}")
         out["secondary_batched_256"] = bench_batched(torch, md, configs, tabs, args)
         log(f"  batched: {out['secondary_batched_256']}")
