@@ -191,6 +191,26 @@ def bench_stable(torch, md, configs, potential, steps):
             "mean_list_length": round(st1["list_entries"] / box.n, 3)}
 
 
+def bench_slab(torch, md, configs, tabs, steps):
+    """The paper's benchmark geometry (Sec. IV-B): an 801,792-atom BCC slab of
+    256 x 261 x 6 cells, open in x and y, periodic through its thickness, at
+    300 K, with the specified potential."""
+    box = configs.config_slab_801792()
+    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    lpa, _ = s.autotune(20)
+    s.step(100)
+    st0 = s.stats()
+    sec, _ = time_steps(torch, s, steps)
+    st1 = s.stats()
+    s.close()
+    return {"workload": "BCC slab 256x261x6 cells, open x/y, periodic z, 300 K",
+            "n_atoms": box.n, "steps": steps, "lanes_per_atom": lpa,
+            "timesteps_per_s": round(steps / sec, 1),
+            "atom_steps_per_s": round(steps / sec * box.n, 1),
+            "rebuilds": int(st1["rebuilds"] - st0["rebuilds"]),
+            "mean_list_length": round(st1["list_entries"] / box.n, 3)}
+
+
 def perf_model(torch, md, configs, tabs, steps: int = 1000):
     """Linear model of the step time at fixed N, t = A n_l + B n_int + C (the
     paper's Eq. linearmodel / Table "regression", with list entries standing
@@ -451,6 +471,9 @@ def main() -> int:
                                  "workload": "74^3 BCC sites - 1% vacancies, 2500 K", **sec_out}
 
     if not args.no_secondary:
+        log("secondary slab 801,792 atoms")
+        out["secondary_slab_801792"] = bench_slab(torch, md, configs, tabs, args.secondary_steps)
+        log(f"  slab: {out['secondary_slab_801792']}")
         out["secondary_stable_128k"] = bench_stable(torch, md, configs, potential, 5000)
         log(f"  stable-lattice context: {out['secondary_stable_128k']}")
         out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)

@@ -47,14 +47,14 @@ typedef int32_t md_status;
 /* Status codes: 0 ok, < 0 error, > 0 warning (sticky bits). */
 #define MD_OK 0
 #define MD_E_ARG (-1)           /* invalid argument */
-#define MD_E_BOX (-2)           /* box edge < 2 (r_cut + skin) or < 3 cells per edge */
+#define MD_E_BOX (-2)           /* periodic edge < 2 (r_cut + skin) or < 3 cells; edge 0 */
 #define MD_E_TABLE (-3)         /* malformed spline table */
 #define MD_E_NBR_OVERFLOW (-4)  /* some atom has more than nbr_capacity list entries */
 #define MD_E_CELL_OVERFLOW (-5) /* some cell holds more than cell_capacity atoms */
 #define MD_E_NONFINITE (-6)     /* non-finite position or force */
 #define MD_E_HIP (-7)           /* HIP runtime error (see md_last_error) */
 #define MD_E_ORDER (-8)         /* call out of order (e.g. md_step before md_build_neighbors) */
-#define MD_E_LOST_ATOM (-9)     /* an atom left the periodic box by more than one box length */
+#define MD_E_LOST_ATOM (-9)     /* an atom moved more than one box length past a periodic edge */
 #define MD_E_WORKSPACE (-10)    /* workspace too small or misaligned */
 #define MD_W_RHO_RANGE 1        /* some rho_i exceeded the F table; last cubic extrapolated */
 
@@ -108,22 +108,32 @@ typedef struct md_stats_t {
 } md_stats_t;
 
 /* Bytes of device workspace md_create needs for these sizes.
- * n_rep replicas; rep_atoms[r] atoms and cubic-or-orthorhombic periodic box
- * rep_box[3r..3r+2] (A) for replica r (host arrays). */
+ * n_rep replicas; rep_atoms[r] atoms and orthorhombic box rep_box[3r..3r+2]
+ * (A) for replica r (host arrays).
+ *
+ * Box convention: a positive length L makes that dimension periodic on
+ * [0, L).  A negative length -E makes it open (free surfaces, as on the
+ * lateral faces of the paper's slab, Sec. IV): no wrap and no image; E is the
+ * extent of the cell grid along it, [0, E).  Atoms of an open dimension may
+ * sit outside [0, E); they are binned into the edge cells, which stays exact
+ * (a cell is at least r_cut + skin wide) but crowds those cells, so choose E
+ * to cover the atoms. */
 md_status md_workspace_size(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
                             const double* rep_box, size_t* bytes);
 
 /* Create a context.  phi(r), rho(r) tables must cover [0, r_cut]; emb(rho)
  * any range (values past its last knot raise MD_W_RHO_RANGE).  workspace is
  * a device pointer of at least md_workspace_size() bytes; stream is a
- * hipStream_t.  Returns MD_E_BOX if any replica edge is below
- * 2 (r_cut + skin) or gives fewer than 3 cells. */
+ * hipStream_t.  Returns MD_E_BOX if a periodic replica edge is below
+ * 2 (r_cut + skin) or gives fewer than 3 cells, or an edge is 0 or not
+ * finite. */
 md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
                     const double* rep_box, const md_spline* phi, const md_spline* rho,
                     const md_spline* emb, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Upload positions x and on-step velocities v (device, [n][3] float64,
- * original order).  Positions are wrapped into the box.  Clears the status
+ * original order).  Positions are wrapped into the box along periodic
+ * dimensions (open ones are kept as given).  Clears the status
  * word; md_build_neighbors must follow before md_step. */
 md_status md_set_state(md_ctx* ctx, const double* x, const double* v);
 

@@ -148,8 +148,15 @@ void or_spline_eval(const or_spline *sp, int64_t n, const double *s, double *f, 
 
 /* ------------------------------------------------------- periodic geometry */
 
-/* One shift into [0, L); a value that lands on L (tiny negative x) becomes 0. */
+/* Boundaries.  A box length L > 0 is a periodic dimension of period L.  A
+ * negative box length marks an open (non-periodic) dimension: no wrap, no
+ * minimum image; cells cover [0, |L|) and atoms outside it belong to the edge
+ * cells. */
+
+/* One shift into [0, L); a value that lands on L (tiny negative x) becomes 0.
+ * Open dimensions are left as they are. */
 static double wrap1(double x, double L) {
+  if (L < 0.0) return x;
   if (x >= L) x -= L;
   else if (x < 0.0) {
     x += L;
@@ -158,22 +165,24 @@ static double wrap1(double x, double L) {
   return x;
 }
 
-/* Minimum image of a separation, valid for |d| < 1.5 L. */
+/* Minimum image of a separation, valid for |d| < 1.5 L (open: unchanged). */
 static double min_image(double d, double L, double half) {
+  if (L < 0.0) return d;
   if (d > half) d -= L;
   else if (d < -half) d += L;
   return d;
 }
 
-/* Wrap every coordinate; returns the number of atoms still outside [0, L) or
- * non-finite afterwards (moved more than one box length in one step). */
+/* Wrap every coordinate; returns the number of coordinates non-finite or, in
+ * a periodic dimension, still outside [0, L) afterwards (moved more than one
+ * box length in one step). */
 int64_t or_wrap(int64_t n, double *x, const double box[3]) {
   int64_t bad = 0;
   for (int64_t i = 0; i < n; ++i) {
     for (int d = 0; d < 3; ++d) {
       double w = wrap1(x[3 * i + d], box[d]);
       x[3 * i + d] = w;
-      if (!(w >= 0.0 && w < box[d])) ++bad;
+      if (!isfinite(w) || (box[d] > 0.0 && !(w >= 0.0 && w < box[d]))) ++bad;
     }
   }
   return bad;
@@ -186,14 +195,16 @@ static double dist2(const double *xi, const double *xj, const double box[3], con
   return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
 }
 
-/* Cell grid: n_d = floor(L_d / r_list) cells per dimension (at least 3),
- * inv_cell_d = n_d / L_d. */
+/* Cell grid: n_d = floor(|L_d| / r_list) cells per dimension (at least 3 when
+ * periodic, at least 1 when open), inv_cell_d = n_d / |L_d|. */
 int32_t or_cell_grid(const double box[3], double rlist, int32_t ncell[3], double inv_cell[3]) {
   for (int d = 0; d < 3; ++d) {
-    double q = floor(box[d] / rlist);
-    if (!(q >= 3.0) || q > 1.0e6) return OR_E_BOX;
+    const double ext = fabs(box[d]);
+    double q = floor(ext / rlist);
+    if (box[d] < 0.0 && q < 1.0) q = 1.0;
+    if (!(q >= (box[d] < 0.0 ? 1.0 : 3.0)) || q > 1.0e6) return OR_E_BOX;
     ncell[d] = (int32_t)q;
-    inv_cell[d] = (double)ncell[d] / box[d];
+    inv_cell[d] = (double)ncell[d] / ext;
   }
   return OR_OK;
 }
@@ -253,8 +264,9 @@ int32_t or_list_brute(int64_t n, const double *x, const double box[3], double rl
 }
 
 /* Same list through a cell grid: candidates are the atoms of the 27 cells
- * around the atom's own cell (periodic), each cell in increasing id.  Falls
- * back to brute force when a dimension has fewer than three cells. */
+ * around the atom's own cell (wrapped in periodic dimensions, cut off at the
+ * grid edge in open ones), each cell in increasing id.  Falls back to brute
+ * force when a periodic dimension has fewer than three cells. */
 int32_t or_list_cells(int64_t n, const double *x, const double box[3], double rlist, int32_t cap,
                       int32_t *cnt, int32_t *nbr) {
   int32_t nc[3];
@@ -279,6 +291,10 @@ int32_t or_list_cells(int64_t n, const double *x, const double box[3], double rl
     for (int dz = -1; dz <= 1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
+          if ((box[0] < 0.0 && (cx + dx < 0 || cx + dx >= nc[0])) ||
+              (box[1] < 0.0 && (cy + dy < 0 || cy + dy >= nc[1])) ||
+              (box[2] < 0.0 && (cz + dz < 0 || cz + dz >= nc[2])))
+            continue;
           int32_t qx = (cx + dx + nc[0]) % nc[0];
           int32_t qy = (cy + dy + nc[1]) % nc[1];
           int32_t qz = (cz + dz + nc[2]) % nc[2];
@@ -443,9 +459,10 @@ int32_t or_md_run(int64_t n, double *x, double *v, double *f, const or_md_params
   memset(st, 0, sizeof(*st));
   int32_t nc[3];
   double ic[3];
-  if (or_cell_grid(p->box, p->r_cut + p->skin, nc, ic) != OR_OK &&
-      (p->box[0] < 2.0 * (p->r_cut + p->skin) || p->box[1] < 2.0 * (p->r_cut + p->skin) ||
-       p->box[2] < 2.0 * (p->r_cut + p->skin)))
+  const double rl = p->r_cut + p->skin;
+  if (or_cell_grid(p->box, rl, nc, ic) != OR_OK &&
+      ((p->box[0] > 0.0 && p->box[0] < 2.0 * rl) || (p->box[1] > 0.0 && p->box[1] < 2.0 * rl) ||
+       (p->box[2] > 0.0 && p->box[2] < 2.0 * rl)))
     return OR_E_BOX;
   size_t nn = (size_t)(n > 0 ? n : 1);
   md_scratch w;

@@ -32,8 +32,9 @@ struct Carve {
 
 struct RepHost {
   int64_t n;
-  double box[3];
+  double box[3];   // lengths (periodic) or cell-grid extents (open)
   int32_t nc[3];
+  int32_t open;    // bit d: dimension d is open
 };
 
 bool valid_spline(const md_spline* s) {
@@ -55,14 +56,20 @@ md_status check_params(const md_params* p) {
   return MD_OK;
 }
 
-// Cells per edge: floor(L / (r_cut + skin)), at least 3; L >= 2 (r_cut + skin)
-// keeps the minimum image unique inside the list radius.
-md_status rep_cells(const md_params* p, const double* box, int32_t nc[3]) {
+// Cells per edge: floor(L / (r_cut + skin)).  A periodic dimension needs at
+// least 3 (and L >= 2 (r_cut + skin), which keeps the minimum image unique
+// inside the list radius); an open one at least 1.
+md_status rep_cells(const md_params* p, const double* box, int32_t open, int32_t nc[3]) {
   const double rl = p->r_cut + p->skin;
   for (int d = 0; d < 3; ++d) {
-    if (!(box[d] >= 2.0 * rl) || !std::isfinite(box[d])) return MD_E_BOX;
-    const double q = std::floor(box[d] / rl);
-    if (q < 3.0 || q > 4096.0) return MD_E_BOX;
+    if (!(box[d] > 0.0) || !std::isfinite(box[d])) return MD_E_BOX;
+    double q = std::floor(box[d] / rl);
+    if ((open >> d) & 1) {
+      q = std::max(q, 1.0);
+    } else if (!(box[d] >= 2.0 * rl) || q < 3.0) {
+      return MD_E_BOX;
+    }
+    if (q > 4096.0) return MD_E_BOX;
     nc[d] = (int32_t)q;
   }
   return MD_OK;
@@ -220,8 +227,15 @@ md_status gather_reps(const md_params* p, int32_t n_rep, const int64_t* rep_atom
     h.n = rep_atoms[r];
     if (h.n < 1) return MD_E_ARG;
     tot += h.n;
-    for (int d = 0; d < 3; ++d) h.box[d] = rep_box[3 * r + d];
-    md_status s = rep_cells(p, h.box, h.nc);
+    // a negative length marks an open dimension; its magnitude is the extent
+    // of the cell grid
+    h.open = 0;
+    for (int d = 0; d < 3; ++d) {
+      const double b = rep_box[3 * r + d];
+      h.box[d] = std::fabs(b);
+      if (b < 0.0) h.open |= 1 << d;
+    }
+    md_status s = rep_cells(p, h.box, h.open, h.nc);
     if (s != MD_OK) return s;
   }
   if (tot >= (int64_t(1) << kIndexBits)) return MD_E_ARG;
@@ -369,7 +383,8 @@ const char* md_status_string(md_status s) {
   switch (s) {
     case MD_OK: return "ok";
     case MD_E_ARG: return "invalid argument";
-    case MD_E_BOX: return "box smaller than 2 (r_cut + skin) or fewer than 3 cells per edge";
+    case MD_E_BOX:
+      return "periodic edge smaller than 2 (r_cut + skin) or fewer than 3 cells, or zero edge";
     case MD_E_TABLE: return "malformed spline table";
     case MD_E_NBR_OVERFLOW: return "neighbour list capacity exceeded";
     case MD_E_CELL_OVERFLOW: return "cell capacity exceeded";
@@ -439,8 +454,6 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   std::vector<AtomTile> at;
   std::vector<CellTile> ct;
   int64_t a0 = 0, c0 = 0;
-  const double rl = p->r_cut + p->skin;
-  (void)rl;
   for (int r = 0; r < n_rep; ++r) {
     RepDev& d = rd[r];
     memset(&d, 0, sizeof(d));
@@ -454,6 +467,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
     d.n_atoms = (int32_t)reps[r].n;
     d.cell0 = (int32_t)c0;
     d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
+    d.open = reps[r].open;
     d.tile0 = (int32_t)at.size();
     d.ntiles = (int32_t)((reps[r].n + 63) / 64);
     for (int64_t t0 = 0; t0 < reps[r].n; t0 += 64)

@@ -55,7 +55,8 @@ struct RepDev {
   int32_t ncell;
   int32_t tile0;   // first atom tile of the replica, in replica order
   int32_t ntiles;  // atom tiles of the replica
-  int32_t pad[2];
+  int32_t open;    // bit d set: dimension d is open (not periodic)
+  int32_t pad;
 };
 
 struct AtomTile {

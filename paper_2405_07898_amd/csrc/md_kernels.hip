@@ -30,6 +30,20 @@ __device__ __forceinline__ double wrap1(double x, double L) {
   return x;
 }
 
+// Wrap into the replica's box in its periodic dimensions; open dimensions keep
+// the coordinate.  `bad` becomes true for a non-finite coordinate or one still
+// outside [0, L) in a periodic dimension (moved more than one box length).
+__device__ __forceinline__ double4 wrap_pos(double4 p, const RepDev& rp, bool& bad) {
+  double q[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool open = (rp.open >> d) & 1;
+    if (!open) q[d] = wrap1(q[d], rp.box[d]);
+    bad = bad || !isfinite(q[d]) || (!open && !(q[d] >= 0.0 && q[d] < rp.box[d]));
+  }
+  return make_double4(q[0], q[1], q[2], p.w);
+}
+
 // 1/sqrt(x) in float64: hardware estimate (relative error below 2^-24 on
 // gfx950, measured), then one Newton-Raphson step y <- y + y/2 (1 - x y^2),
 // which leaves a relative error of a few 1e-15 (the paper evaluates
@@ -106,14 +120,10 @@ __global__ __launch_bounds__(64) void k_import(Geometry g, State s, const double
   if ((int)threadIdx.x >= tl.count) return;
   const RepDev& rp = g.reps[tl.rep];
   const int64_t i = tl.begin + threadIdx.x;
-  double4 p;
-  p.x = wrap1(x[3 * i + 0], rp.box[0]);
-  p.y = wrap1(x[3 * i + 1], rp.box[1]);
-  p.z = wrap1(x[3 * i + 2], rp.box[2]);
-  p.w = 0.0;
-  if (!(p.x >= 0.0 && p.x < rp.box[0] && p.y >= 0.0 && p.y < rp.box[1] && p.z >= 0.0 &&
-        p.z < rp.box[2]))
-    set_bits(s.status, ST_LOST);
+  bool bad = false;
+  const double4 p =
+      wrap_pos(make_double4(x[3 * i + 0], x[3 * i + 1], x[3 * i + 2], 0.0), rp, bad);
+  if (bad) set_bits(s.status, ST_LOST);
   s.pos[i] = p;
   s.vel[i] = make_double4(v[3 * i + 0], v[3 * i + 1], v[3 * i + 2], 0.0);
   s.id[i] = (int32_t)i;
@@ -130,9 +140,11 @@ __global__ __launch_bounds__(64) void k_export(Geometry g, State s, double* __re
   const int64_t o = s.id[i];
   const double4 p = s.pos[i];
   if (x) {
-    x[3 * o + 0] = wrap1(p.x, rp.box[0]);
-    x[3 * o + 1] = wrap1(p.y, rp.box[1]);
-    x[3 * o + 2] = wrap1(p.z, rp.box[2]);
+    bool bad = false;
+    const double4 q = wrap_pos(p, rp, bad);
+    x[3 * o + 0] = q.x;
+    x[3 * o + 1] = q.y;
+    x[3 * o + 2] = q.z;
   }
   const double4 fr = s.frc[i];
   if (v) {
@@ -193,12 +205,9 @@ __device__ __forceinline__ void bin_tile(const Geometry& g, const State& s, cons
   if (rcond && rcond[tl.rep] == 0) return;  // this replica keeps its list
   const RepDev& rp = g.reps[tl.rep];
   const int64_t i = tl.begin + threadIdx.x;
-  double4 p = s.pos[i];
-  p.x = wrap1(p.x, rp.box[0]);
-  p.y = wrap1(p.y, rp.box[1]);
-  p.z = wrap1(p.z, rp.box[2]);
-  if (!(p.x >= 0.0 && p.x < rp.box[0] && p.y >= 0.0 && p.y < rp.box[1] && p.z >= 0.0 &&
-        p.z < rp.box[2])) {
+  bool bad = false;
+  const double4 p = wrap_pos(s.pos[i], rp, bad);
+  if (bad) {
     set_bits(s.status, ST_LOST);
     return;
   }
@@ -322,11 +331,17 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
     const int dz = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dx = lane % 3 - 1;
     const int32_t ux = cx + dx, uy = cy + dy, uz = cz + dz;
     // wrapped index below 0: candidate near L, shift -L (code 0); above: +L (code 2)
-    const uint32_t kx = ux < 0 ? 0u : (ux >= nx ? 2u : 1u);
-    const uint32_t ky = uy < 0 ? 0u : (uy >= ny ? 2u : 1u);
-    const uint32_t kz = uz < 0 ? 0u : (uz >= nz ? 2u : 1u);
+    uint32_t kx = ux < 0 ? 0u : (ux >= nx ? 2u : 1u);
+    uint32_t ky = uy < 0 ? 0u : (uy >= ny ? 2u : 1u);
+    uint32_t kz = uz < 0 ? 0u : (uz >= nz ? 2u : 1u);
+    // an open dimension has no image: a stencil cell past its grid edge is empty
+    const bool outside = (((rp.open & 1) && kx != 1u) || ((rp.open & 2) && ky != 1u) ||
+                          ((rp.open & 4) && kz != 1u));
+    if (rp.open & 1) kx = 1u;
+    if (rp.open & 2) ky = 1u;
+    if (rp.open & 4) kz = 1u;
     const int32_t q = rp.cell0 + (((uz + nz) % nz) * ny + (uy + ny) % ny) * nx + (ux + nx) % nx;
-    n = min(s.bin_cnt[q], ccap);
+    n = outside ? 0 : min(s.bin_cnt[q], ccap);
     L.q[lane] = q;
     L.n[lane] = n;
     L.code[lane] = (int32_t)(kx | (ky << 2) | (kz << 4));

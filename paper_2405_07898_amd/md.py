@@ -148,7 +148,10 @@ def make_params(*, mass, dt, r_cut, skin, ftm2v, kboltz=8.617333262e-5, precisio
 
 
 class System:
-    """One context: n_rep periodic boxes advanced together on one GPU.
+    """One context: n_rep boxes advanced together on one GPU.
+
+    A box length L > 0 makes that dimension periodic; L < 0 makes it open
+    with a cell grid of extent |L|.
 
     x, v: (N, 3) float64 (numpy or torch); boxes: (n_rep, 3); rep_atoms: (n_rep,).
     Device memory (workspace, state staging) is allocated through torch.

@@ -44,3 +44,36 @@ def test_status_strings_without_gpu():
     lib.md_status_string.restype = ctypes.c_char_p
     assert lib.md_status_string(0) == b"ok"
     assert b"capacity" in lib.md_status_string(-4)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+@pytest.mark.parametrize("box,ok", [
+    ((20.0, 20.0, 20.0), True),
+    ((10.0, 20.0, 20.0), False),    # periodic edge below 2 (r_cut + skin) = 10.6
+    ((-3.0, -3.0, -3.0), True),     # open edges: any positive extent, one cell
+    ((-3.0, -3.0, 10.0), False),    # the periodic edge is still checked
+    ((-40.0, -40.0, 16.5), True),   # a slab: open x, y, periodic z with 3 cells
+    ((0.0, 20.0, 20.0), False),
+    ((-0.0, 20.0, 20.0), False),
+    ((float("inf"), 20.0, 20.0), False),
+    ((-float("nan"), 20.0, 20.0), False),
+])
+def test_box_validation_without_gpu(box, ok):
+    """md_workspace_size validates the box on the host: a positive length is a
+    periodic edge, a negative one an open edge of that extent."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0)
+    n = (ctypes.c_int64 * 1)(1000)
+    b = np.array(box, dtype=np.float64)
+    out = ctypes.c_size_t(0)
+    rc = lib.md_workspace_size(ctypes.byref(p), 1, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(out))
+    assert (rc == 0) == ok, rc
+    if not ok:
+        assert rc == -2
+    else:
+        assert out.value > 0

@@ -333,3 +333,70 @@ def test_overflow_and_box_errors(oracle_lib, md_tables):
     tiny = configs.small_box(3, seed=27)
     _, out = _run(tiny, md_tables, 1, 1.0)
     assert out["code"] == oracle_lib.OR_E_BOX
+
+
+# ----------------------------------------------------------------- open boundaries
+
+def _numpy_sets(x, box, rlist):
+    """All-pairs neighbour sets by numpy: minimum image only where box > 0."""
+    d = x[None, :, :] - x[:, None, :]
+    per = box > 0
+    L = np.abs(box)
+    d[..., per] -= L[per] * np.round(d[..., per] / L[per])
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    return [frozenset(np.nonzero(r[i] < rlist)[0].tolist()) for i in range(x.shape[0])], r
+
+
+@pytest.mark.parametrize("sigma", [0.01, 0.2])
+def test_open_slab_lists(oracle_lib, sigma):
+    """Open x, y (negative box lengths), periodic z: cell list = brute force =
+    numpy all-pairs with the minimum image in z only; no pair across the open
+    edges."""
+    b = configs.slab(7, 6, 5, seed=21, sigma_x=sigma, vacuum=6.0)
+    c1, n1, _ = oracle_lib.neighbor_list(b.x, b.box, RC + SKIN, method="cells")
+    c2, n2, _ = oracle_lib.neighbor_list(b.x, b.box, RC + SKIN, method="brute")
+    want, r = _numpy_sets(b.x, b.box, RC + SKIN)
+    assert not np.any(np.abs(r - (RC + SKIN)) < 1e-9)
+    assert oracle_lib.neighbor_sets(c1, n1) == want
+    assert oracle_lib.neighbor_sets(c2, n2) == want
+    # an atom on the low-x face has no neighbour on the high-x face
+    lo = np.argmin(b.x[:, 0])
+    hi = set(np.nonzero(b.x[:, 0] > b.x[:, 0].max() - 1.0)[0].tolist())
+    assert not (want[lo] & hi)
+
+
+def test_open_slab_forces(oracle_lib, md_tables):
+    """Open slab: net force zero (Newton's third law holds pair by pair) and
+    F = -grad U by central differences, surface atoms included."""
+    b = configs.slab(6, 6, 5, seed=22, sigma_x=0.05, vacuum=6.0)
+    res = oracle_lib.forces_at(b.x, b.box, md_tables, RC, SKIN)
+    net = np.abs(res["f"].sum(axis=0))
+    assert np.all(net <= 1e-12 * np.abs(res["f"]).sum())
+    # surface atoms carry a net inward force of order eV/A, interior ones ~0
+    assert np.abs(res["f"][:, 0]).max() > 0.1
+    rng = np.random.default_rng(3)
+    h = 1e-4
+    for i in np.concatenate([[int(np.argmin(b.x[:, 0]))], rng.integers(b.n, size=6)]):
+        for d in range(3):
+            xp, xm = b.x.copy(), b.x.copy()
+            xp[i, d] += h
+            xm[i, d] -= h
+            ep = oracle_lib.forces_at(xp, b.box, md_tables, RC, SKIN)["pe"]
+            em = oracle_lib.forces_at(xm, b.box, md_tables, RC, SKIN)["pe"]
+            assert abs(-(ep - em) / (2 * h) - res["f"][i, d]) < 1e-7
+
+
+# rho(r) >= 0.5, as for the periodic dimer
+@pytest.mark.parametrize("r", [2.3, 2.6])
+def test_dimer_in_open_box(oracle_lib, md_tables, r):
+    """All three dimensions open: a dimer is the closed form with no image at all,
+    even when the open box is shorter than twice the list radius."""
+    x = np.array([[1.0, 1.0, 1.0], [1.0 + r, 1.0, 1.0]])
+    box = -np.array([6.0, 3.0, 3.0])
+    res = oracle_lib.forces_at(x, box, md_tables, RC, SKIN)
+    e = P.phi(r) + 2 * P.emb(P.rho(r))
+    s = P.dphi(r) + 2 * P.demb(P.rho(r)) * P.drho(r)
+    assert abs(res["pe"] - e) < 1e-6
+    np.testing.assert_allclose(res["f"][0], [s, 0, 0], atol=1e-6)
+    np.testing.assert_allclose(res["f"][1], [-s, 0, 0], atol=1e-6)

@@ -135,3 +135,42 @@ def small_box(n_cells: int, seed: int, *, sigma_x: float = 0.01, temperature: fl
     """Tiny test boxes with the same recipe."""
     return make_box(n_cells, np.random.default_rng(seed), vacancy_fraction=vacancy_fraction,
                     sigma_x=sigma_x, temperature=temperature, a=a)
+
+
+# --- slab with open lateral boundaries --------------------------------------
+
+def bcc_block(nx: int, ny: int, nz: int, a: float = A_LAT) -> np.ndarray:
+    """Sites of an nx x ny x nz BCC block, site id = ((ix*ny + iy)*nz + iz)*2 + b."""
+    ix, iy, iz = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                             np.arange(nz, dtype=np.float64), indexing="ij")
+    base = np.stack([ix, iy, iz], axis=-1).reshape(-1, 1, 3)
+    basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])
+    return ((base + basis[None]) * a).reshape(-1, 3)
+
+
+def slab(nx: int, ny: int, nz: int, seed: int, *, vacuum: float = 12.0,
+         temperature: float = 300.0, sigma_x: float = 0.01, a: float = A_LAT) -> Box:
+    """A thin BCC slab, open in x and y, periodic in z (the paper's geometry:
+    thin slabs with open lateral boundaries, Sec. IV-B).  The block sits
+    `vacuum` A inside the lower x and y cell-grid edges; the box lengths of
+    the open dimensions are negative (the convention of both the oracle and
+    the library: a negative length marks an open dimension and gives the
+    extent of its cell grid)."""
+    rng = np.random.default_rng(seed)
+    x = bcc_block(nx, ny, nz, a)
+    x = x + sigma_x * rng.standard_normal(x.shape)
+    x[:, 0] += vacuum
+    x[:, 1] += vacuum
+    lz = nz * a
+    x[:, 2] = np.mod(x[:, 2], lz)
+    x[:, 2] = np.where(x[:, 2] >= lz, 0.0, x[:, 2])
+    box = np.array([-(nx * a + 2.0 * vacuum), -(ny * a + 2.0 * vacuum), lz])
+    v = maxwell_boltzmann(rng, x.shape[0], temperature)
+    return Box(x=x, v=v, box=box, n_cells=nx, temperature=temperature,
+               site_ids=np.arange(x.shape[0], dtype=np.int64))
+
+
+def config_slab_801792() -> Box:
+    """The paper's benchmark slab shape: 256 x 261 x 6 BCC cells = 801,792 atoms,
+    open in x and y, 300 K, seed 6."""
+    return slab(256, 261, 6, 6)
