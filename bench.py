@@ -211,6 +211,37 @@ def bench_slab(torch, md, configs, tabs, steps):
             "mean_list_length": round(st1["list_entries"] / box.n, 3)}
 
 
+def bench_half(torch, md, configs, tabs, steps):
+    """Force symmetry: the 128,000-atom workload with the half-list form (each
+    pair evaluated once, two-phase deterministic reduction), against the
+    full-list form on the same box and schedule."""
+    from workloads import potential
+
+    box = configs.config_128k()
+    out = {"n_atoms": box.n, "steps": steps}
+    for name, mode in (("full", md.MD_LIST_FULL), ("half", md.MD_LIST_HALF)):
+        p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+                           ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
+                           nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY,
+                           list_mode=mode)
+        s = md.System(p, tabs, [box.n], box.box[None, :])
+        s.set_state(box.x, box.v)
+        s.build_neighbors()
+        lpa, _ = s.autotune(20)
+        s.step(100)
+        st0 = s.stats()
+        sec, _ = time_steps(torch, s, steps)
+        st1 = s.stats()
+        dens = time_kernel(torch, s, md, md.PASS_DENSITY, 50)
+        frc = time_kernel(torch, s, md, md.PASS_FORCE_RAW, 50)
+        s.close()
+        out[name] = {"timesteps_per_s": round(steps / sec, 1), "lanes_per_atom": lpa,
+                     "density_pass_us": round(dens, 3), "force_pass_us": round(frc, 3),
+                     "rebuilds": int(st1["rebuilds"] - st0["rebuilds"]),
+                     "mean_list_length": round(st1["list_entries"] / box.n, 3)}
+    return out
+
+
 def perf_model(torch, md, configs, tabs, steps: int = 1000):
     """Linear model of the step time at fixed N, t = A n_l + B n_int + C (the
     paper's Eq. linearmodel / Table "regression", with list entries standing
@@ -474,6 +505,8 @@ def main() -> int:
         log("secondary slab 801,792 atoms")
         out["secondary_slab_801792"] = bench_slab(torch, md, configs, tabs, args.secondary_steps)
         log(f"  slab: {out['secondary_slab_801792']}")
+        out["secondary_half_list_128k"] = bench_half(torch, md, configs, tabs, 5000)
+        log(f"  half list: {out['secondary_half_list_128k']}")
         out["secondary_stable_128k"] = bench_stable(torch, md, configs, potential, 5000)
         log(f"  stable-lattice context: {out['secondary_stable_128k']}")
         out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)

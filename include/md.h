@@ -64,6 +64,18 @@ typedef int32_t md_status;
                       (TwoSum) accumulation; positions, velocities, integration
                       and energy totals in float64 */
 
+/* Neighbour-list form of the pair passes.
+ * MD_LIST_FULL: every atom walks both directions of each pair and writes only
+ *   itself (each pair term is evaluated twice).
+ * MD_LIST_HALF: force symmetry (the paper's Sec. VI-A projection): each pair is
+ *   evaluated once, by its lower-slot atom, into a pair slot; a second pass
+ *   gathers every atom's pair slots in a fixed (sorted) order.  Deterministic
+ *   (no float atomics; bitwise repeatable), float64 only (MD_FP64), one lane
+ *   per atom (lanes_per_atom is ignored).  Takes 52 + 52 nbr_capacity extra
+ *   bytes per atom of workspace. */
+#define MD_LIST_FULL 0
+#define MD_LIST_HALF 1
+
 /* A cubic spline on equally spaced knots x0 + k/inv_dx, k = 0..n_knots-1.
  * coef (host) holds (n_knots-1) rows of 4 float64: segment k evaluates
  * c0 + c1 t + c2 t^2 + c3 t^3 with t = (s - x0) inv_dx - k in [0,1); the
@@ -92,6 +104,8 @@ typedef struct md_params {
   int32_t chunk_steps;   /* steps per captured hipGraph (even, >= 2), e.g. 100 */
   int32_t lanes_per_atom;/* 0 = automatic, else 1, 2, 4 or 8 lanes per atom */
   int32_t sort_every;    /* re-sort atoms by cell every this many chunks (0 = never) */
+  int32_t list_mode;     /* MD_LIST_FULL or MD_LIST_HALF */
+  int32_t reserved;      /* 0 */
 } md_params;
 
 typedef struct md_ctx md_ctx;

@@ -53,6 +53,9 @@ md_status check_params(const md_params* p) {
   const int l = p->lanes_per_atom;
   if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8)) return MD_E_ARG;
   if (p->sort_every < 0) return MD_E_ARG;
+  if (p->list_mode != MD_LIST_FULL && p->list_mode != MD_LIST_HALF) return MD_E_ARG;
+  // the half-list passes exist in float64 only
+  if (p->list_mode == MD_LIST_HALF && p->precision != MD_FP64) return MD_E_ARG;
   return MD_OK;
 }
 
@@ -113,6 +116,7 @@ struct md_ctx {
   int32_t* status = nullptr;
   int cur = 0;
   int lpa = 1;
+  bool half = false;    // half-list pair passes
   bool has_state = false;
   bool built = false;
   bool v_half = false;  // velocities are half-step (after build)
@@ -171,6 +175,11 @@ struct Buffers {
   int32_t* sort_id;
   double4 *snap_pos, *snap_vel;
   double *partial, *energy;
+  // half-list form only
+  uint32_t *hnbr, *rslot_u, *rslot;
+  int32_t *hcnt, *rcnt, *rfill;
+  double *pval, *own_rho;
+  double4 *qval, *own_f;
 };
 
 size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s, int nr, int ne,
@@ -214,6 +223,23 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.snap_vel = c.take<double4>(N);
   o.partial = c.take<double>(2 * s.atile_blocks);
   o.energy = c.take<double>(2 * (size_t)n_rep);
+  o.hnbr = o.rslot_u = o.rslot = nullptr;
+  o.hcnt = o.rcnt = o.rfill = nullptr;
+  o.pval = o.own_rho = nullptr;
+  o.qval = o.own_f = nullptr;
+  if (p->list_mode == MD_LIST_HALF) {
+    const size_t slots = N * (size_t)p->nbr_capacity;
+    o.hnbr = c.take<uint32_t>(slots);
+    o.rslot_u = c.take<uint32_t>(slots);
+    o.rslot = c.take<uint32_t>(slots);
+    o.hcnt = c.take<int32_t>(N);
+    o.rcnt = c.take<int32_t>(N);
+    o.rfill = c.take<int32_t>(N);
+    o.pval = c.take<double>(slots);
+    o.qval = c.take<double4>(slots);
+    o.own_rho = c.take<double>(N);
+    o.own_f = c.take<double4>(N);
+  }
   return (c.off + 255) & ~size_t(255);
 }
 
@@ -266,6 +292,39 @@ md_status status_code(int32_t bits) {
   return MD_OK;
 }
 
+// The pair passes in the context's list form.  cond: device flag of a
+// rebuild in this step (the half form re-derives its half list then).
+hipError_t density_pass(md_ctx* c, const State& s, int lpa, const double4* pos,
+                        const int32_t* cond, int32_t* clear_flag, int32_t* rclear, bool want_rho) {
+  if (c->half)
+    return launch_half_density(c->L, c->g, s, c->t, pos, cond, false, clear_flag, rclear,
+                               c->sz.cells, want_rho);
+  return launch_density(c->L, c->g, s, c->t, c->p.precision, lpa, pos, cond, clear_flag, rclear,
+                        c->sz.cells, want_rho);
+}
+
+hipError_t force_integrate_pass(md_ctx* c, const State& s, int lpa, const double4* pos_in,
+                                double4* pos_out, int32_t* flag_next, int32_t* rflag_next) {
+  if (c->half)
+    return launch_half_force_integrate(c->L, c->g, s, c->t, pos_in, pos_out, flag_next,
+                                       rflag_next);
+  return launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, lpa, pos_in, pos_out,
+                                flag_next, rflag_next);
+}
+
+hipError_t force_only_pass(md_ctx* c, const State& s, const double4* pos) {
+  if (c->half) return launch_half_force_only(c->L, c->g, s, c->t, pos);
+  return launch_force_only(c->L, c->g, s, c->t, c->p.precision, c->lpa, pos);
+}
+
+// After an eager list build: the half form's half list and reverse slots
+// (the density passes derive them; their rho and F' are recomputed later).
+hipError_t half_reindex(md_ctx* c, const State& s) {
+  if (!c->half) return hipSuccess;
+  return launch_half_density(c->L, c->g, s, c->t, s.pos, nullptr, true, nullptr, nullptr,
+                             c->sz.cells, false);
+}
+
 // Sort by cell (new slot order), then bin and build the list, leaving the
 // bins zeroed.  Positions are wrapped; x_ref is reset.
 md_status rebuild_sorted(md_ctx* c, bool sort) {
@@ -277,14 +336,14 @@ md_status rebuild_sorted(md_ctx* c, bool sort) {
   HIPC(c, launch_bin(c->L, c->g, s, nullptr, nullptr));
   HIPC(c, launch_build(c->L, c->g, s, nullptr, nullptr));
   HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+  HIPC(c, half_reindex(c, s));
   return MD_OK;
 }
 
 md_status forces_now(md_ctx* c, bool want_rho) {
   State& s = c->st[c->cur];
-  HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, nullptr, nullptr,
-                         nullptr, c->sz.cells, want_rho));
-  HIPC(c, launch_force_only(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos));
+  HIPC(c, density_pass(c, s, c->lpa, s.pos, nullptr, nullptr, nullptr, want_rho));
+  HIPC(c, force_only_pass(c, s, s.pos));
   return MD_OK;
 }
 
@@ -298,10 +357,8 @@ md_status step_eager(md_ctx* c) {
   int32_t* rf_nxt = s.rflag + (k == 0 ? c->n_rep : 0);
   HIPC(c, launch_bin(c->L, c->g, s, fl_cur, rf_cur));
   HIPC(c, launch_build(c->L, c->g, s, fl_cur, rf_cur));
-  HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, fl_cur, fl_nxt,
-                         rf_nxt, c->sz.cells, false));
-  HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
-                                 c->st[1 - k].pos, fl_nxt, rf_nxt));
+  HIPC(c, density_pass(c, s, c->lpa, s.pos, fl_cur, fl_nxt, rf_nxt, false));
+  HIPC(c, force_integrate_pass(c, s, c->lpa, s.pos, c->st[1 - k].pos, fl_nxt, rf_nxt));
   c->cur = 1 - k;
   return MD_OK;
 }
@@ -511,6 +568,9 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   if (e == hipSuccess) e = hipMemset(b.rflag, 0, 3 * (size_t)n_rep * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.cell_stat, 0, 3 * (size_t)ls.cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.frc, 0, (size_t)ls.n * sizeof(double4));
+  if (e == hipSuccess && b.rfill) e = hipMemset(b.rfill, 0, (size_t)ls.n * sizeof(int32_t));
+  if (e == hipSuccess && b.hcnt) e = hipMemset(b.hcnt, 0, (size_t)ls.n * sizeof(int32_t));
+  if (e == hipSuccess && b.rcnt) e = hipMemset(b.rcnt, 0, (size_t)ls.n * sizeof(int32_t));
   if (e != hipSuccess) {
     md_status r_ = hip_fail(c, e, "hipMemset");
     delete c;
@@ -568,6 +628,7 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
       return MD_E_TABLE;
     }
     e2 = allow_pair_lds(t, p->precision);
+    if (e2 == hipSuccess && p->list_mode == MD_LIST_HALF) e2 = allow_half_lds(t);
     if (e2 != hipSuccess) {
       md_status r_ = hip_fail(c, e2, "hipFuncSetAttribute");
       delete c;
@@ -595,6 +656,17 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   base.sort_vel = b.sort_vel;
   base.sort_id = b.sort_id;
   base.partial = b.partial;
+  base.hnbr = b.hnbr;
+  base.hcnt = b.hcnt;
+  base.rslot_u = b.rslot_u;
+  base.rslot = b.rslot;
+  base.rcnt = b.rcnt;
+  base.rfill = b.rfill;
+  base.pval = b.pval;
+  base.qval = b.qval;
+  base.own_rho = b.own_rho;
+  base.own_f = b.own_f;
+  c->half = (p->list_mode == MD_LIST_HALF);
   c->st[0] = base;
   c->st[1] = base;
   c->st[0].pos = b.pos0;
@@ -782,26 +854,23 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
   switch (pass) {
     case 0:
       for (int r = 0; r < reps; ++r)
-        HIPC(c, launch_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos, nullptr,
-                               nullptr, nullptr, c->sz.cells, false));
+        HIPC(c, density_pass(c, s, c->lpa, s.pos, nullptr, nullptr, nullptr, false));
       break;
     case 1:
       // the kernel md_step runs, writing the other position buffer; positions,
       // velocities and the step counter come back from a snapshot afterwards
       HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, false));
       for (int r = 0; r < reps; ++r)
-        HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
-                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
-                                       s.rflag + 2 * c->n_rep));
+        HIPC(c, force_integrate_pass(c, s, c->lpa, s.pos, c->st[1 - c->cur].pos,
+                                     c->status + SW_SCRATCH, s.rflag + 2 * c->n_rep));
       HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, true));
       break;
     case 4:
       // the same kernel with no snapshot around it: velocities advance on every
       // launch while positions are read from the unchanged current buffer
       for (int r = 0; r < reps; ++r)
-        HIPC(c, launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, c->lpa, s.pos,
-                                       c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
-                                       s.rflag + 2 * c->n_rep));
+        HIPC(c, force_integrate_pass(c, s, c->lpa, s.pos, c->st[1 - c->cur].pos,
+                                     c->status + SW_SCRATCH, s.rflag + 2 * c->n_rep));
       break;
     case 2:
       // list build from freshly filled bins (one binning first, bins zeroed after)
@@ -809,6 +878,7 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
       HIPC(c, launch_bin(c->L, c->g, s, nullptr, nullptr));
       for (int r = 0; r < reps; ++r) HIPC(c, launch_build(c->L, c->g, s, nullptr, nullptr));
       HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+      HIPC(c, half_reindex(c, s));
       break;
     default:
       // binning (wraps positions and resets x_ref), then one build keeps the list consistent
@@ -844,6 +914,8 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
   HIPC(c, hipEventCreate(&e0));
   HIPC(c, hipEventCreate(&e1));
   const int cand[4] = {1, 2, 4, 8};
+  // the half-list passes run one lane per atom: time that one schedule
+  const int n_cand = c->half ? 1 : 4;
   float per[4] = {3.4e38f, 3.4e38f, 3.4e38f, 3.4e38f};
   md_status rc = MD_OK;
   // the step's own kernels (density, then forces with the integration) on the
@@ -852,7 +924,7 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
   HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, false));
   // two sweeps over the candidates, keeping each one's faster sweep
   for (int sweep = 0; sweep < 2 && rc == MD_OK; ++sweep) {
-    for (int q = 0; q < 4 && rc == MD_OK; ++q) {
+    for (int q = 0; q < n_cand && rc == MD_OK; ++q) {
       const int l = cand[q];
       // one untimed round, then reps timed rounds
       for (int r = 0; r <= reps && rc == MD_OK; ++r) {
@@ -860,12 +932,10 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
           hipError_t e = hipEventRecord(e0, c->L.stream);
           if (e != hipSuccess) rc = hip_fail(c, e, "hipEventRecord");
         }
-        hipError_t e = launch_density(c->L, c->g, s, c->t, c->p.precision, l, s.pos, nullptr,
-                                      nullptr, nullptr, c->sz.cells, false);
+        hipError_t e = density_pass(c, s, l, s.pos, nullptr, nullptr, nullptr, false);
         if (e == hipSuccess)
-          e = launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, l, s.pos,
-                                     c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
-                                     s.rflag + 2 * c->n_rep);
+          e = force_integrate_pass(c, s, l, s.pos, c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
+                                   s.rflag + 2 * c->n_rep);
         if (e != hipSuccess) rc = hip_fail(c, e, "autotune launch");
       }
       if (rc != MD_OK) break;
@@ -886,7 +956,7 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
   }
   float best = 3.4e38f;
   int pick = c->lpa;
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < n_cand; ++q)
     if (per[q] < best) {
       best = per[q];
       pick = cand[q];

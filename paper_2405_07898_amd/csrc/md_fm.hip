@@ -388,6 +388,8 @@ md_params internal_params(double r_cut, int32_t cap) {
   p.chunk_steps = 2;
   p.lanes_per_atom = 1;
   p.sort_every = 0;
+  p.list_mode = MD_LIST_FULL;
+  p.reserved = 0;
   return p;
 }
 

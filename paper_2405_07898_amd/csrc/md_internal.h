@@ -129,6 +129,17 @@ struct State {
   double4* sort_vel;
   int32_t* sort_id;
   double* partial;   // per-atom-tile energy partials [n_atiles][2]
+  // half-list form (null for the full list): pair slot (k, i) = k N + i
+  uint32_t* hnbr;    // [cap][n] entries of i's list with j > i, in list order
+  int32_t* hcnt;     // entries of hnbr per atom
+  uint32_t* rslot_u; // [cap][n] pair slots where the atom is the j side, unsorted
+  uint32_t* rslot;   // the same, ascending
+  int32_t* rcnt;     // entries of rslot per atom
+  int32_t* rfill;    // scatter counters (zero between rebuilds)
+  double* pval;      // [cap][n] rho(r) of each pair slot
+  double4* qval;     // [cap][n] force on the i side of each pair slot (w unused)
+  double* own_rho;   // [n] sum over the atom's own pair slots
+  double4* own_f;    // [n] force sum over the atom's own pair slots
 };
 
 // ---------------------------------------------------------------- launchers
@@ -161,6 +172,19 @@ hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s,
 size_t density_lds_bytes(const Tables& t, int precision);
 size_t force_lds_bytes(const Tables& t, int precision);
 hipError_t allow_pair_lds(const Tables& t, int precision);
+// Half-list form of the pair passes (md_half.hip).  `reindex` rebuilds the
+// half list and the sorted reverse slots from the full list first (cond: the
+// device flag of a rebuild in this step; force: do it regardless).
+hipError_t launch_half_density(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                               const double4* pos, const int32_t* cond, bool force_reindex,
+                               int32_t* clear_flag, int32_t* rclear, int64_t n_cells_total,
+                               bool want_rho);
+hipError_t launch_half_force_integrate(const Launch& L, const Geometry& g, const State& s,
+                                       const Tables& t, const double4* pos_in, double4* pos_out,
+                                       int32_t* flag_next, int32_t* rflag_next);
+hipError_t launch_half_force_only(const Launch& L, const Geometry& g, const State& s,
+                                  const Tables& t, const double4* pos);
+hipError_t allow_half_lds(const Tables& t);
 hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double scale);
 hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                          double* out_pe_ke, int32_t n_rep);

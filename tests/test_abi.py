@@ -77,3 +77,34 @@ def test_box_validation_without_gpu(box, ok):
         assert rc == -2
     else:
         assert out.value > 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+@pytest.mark.parametrize("prec,mode,ok", [(0, 0, True), (1, 0, True), (0, 1, True), (1, 1, False),
+                                          (0, 2, False)])
+def test_list_mode_validation_without_gpu(prec, mode, ok):
+    """The half-list form exists in float64 only; unknown list forms are rejected."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0, precision=prec,
+                       list_mode=mode)
+    n = (ctypes.c_int64 * 1)(1000)
+    b = np.array([20.0, 20.0, 20.0])
+    full = ctypes.c_size_t(0)
+    out = ctypes.c_size_t(0)
+    rc = lib.md_workspace_size(ctypes.byref(p), 1, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(out))
+    assert (rc == 0) == ok
+    if not ok:
+        assert rc == -1
+    elif mode == 1:
+        # the half form's pair slots: 52 + 52 cap bytes per atom more than the full list
+        p0 = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0)
+        lib.md_workspace_size(ctypes.byref(p0), 1, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(full))
+        extra = out.value - full.value
+        per_atom = 52 + 52 * 128
+        assert per_atom * 1000 <= extra <= per_atom * 1000 + 11 * 256
