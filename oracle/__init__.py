@@ -84,6 +84,10 @@ def lib():
             "or_forces_at": (i32, [i64, pd, pd, d, d, i32, P(Spline), P(Spline), P(Spline), pd, pd,
                                    pd, pd]),
             "or_forces_analytic": (i32, [i64, pd, pd, P(Analytic), pd, pd]),
+            "or_forces_at_multi": (i32, [i64, pd, pd, d, d, i32, i32, pi, P(Spline), P(Spline),
+                                         P(Spline), pd, pd, pd, pd]),
+            "or_md_run_multi": (i32, [i64, pd, pd, pd, P(MDParams), i32, pi, pd, P(Spline),
+                                      P(Spline), P(Spline), i64, pd, P(MDStats)]),
             "or_fm_loss_grad": (d, [i32, P(i64), pd, pd, d, P(Spline), P(Spline), P(Spline), pd,
                                     pd, pd, pd, pd]),
         }
@@ -287,3 +291,64 @@ def fm_loss_grad(x, offsets, boxes, tables, fref, rc=5.0, want_grad=True):
                                  refs[2].ref, _pd(fref), _pd(grads[0]), _pd(grads[1]),
                                  _pd(grads[2]), _pd(f))
     return float(loss), grads, f
+
+
+# ---------------------------------------------------------------- several atom types
+
+class _SplineArray:
+    """A contiguous C array of spline structs (and the coefficient arrays behind it)."""
+
+    def __init__(self, tables):
+        self.refs = [_SplineRef(t) for t in tables]
+        self.arr = (Spline * len(self.refs))(*[r.s for r in self.refs])
+
+    @property
+    def ptr(self):
+        return C.cast(self.arr, C.POINTER(Spline))
+
+
+def _multi_tables(tabs):
+    """tabs = (phi[a][b], rho[t], emb[t]) -> (n_types, phi array (row-major a, b), rho, emb)."""
+    phi, rho, emb = tabs
+    nt = len(rho)
+    assert len(emb) == nt and len(phi) == nt and all(len(row) == nt for row in phi)
+    return nt, _SplineArray([phi[a][b] for a in range(nt) for b in range(nt)]), \
+        _SplineArray(rho), _SplineArray(emb)
+
+
+def forces_at_multi(x, box, types, tabs, rc, skin=0.0, cap=256):
+    """Multi-species forces, rho, F' and potential energy (list built at rc + skin)."""
+    x = _f64(x)
+    n = x.shape[0]
+    t = np.ascontiguousarray(types, np.int32)
+    nt, ph, rh, em = _multi_tables(tabs)
+    assert t.shape == (n,) and (n == 0 or (t.min() >= 0 and t.max() < nt))
+    f, r, fp = np.empty((n, 3)), np.empty(n), np.empty(n)
+    pe = C.c_double()
+    code = lib().or_forces_at_multi(n, _pd(x), _pd(_f64(box)), float(rc), float(skin), int(cap),
+                                    nt, _pi(t), ph.ptr, rh.ptr, em.ptr, _pd(f), _pd(r), _pd(fp),
+                                    C.byref(pe))
+    if code < 0:
+        raise RuntimeError(f"oracle forces_at_multi failed: {code}")
+    return dict(f=f, rho=r, fp=fp, pe=pe.value, flags=code)
+
+
+def md_run_multi(x, v, box, types, tabs, masses, nsteps, *, dt, r_cut, skin, ftm2v, cap=128,
+                 want_energy=False):
+    """Multi-species velocity-Verlet run (per-type masses)."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    n = x.shape[0]
+    t = np.ascontiguousarray(types, np.int32)
+    nt, ph, rh, em = _multi_tables(tabs)
+    m = _f64(masses)
+    assert m.shape == (nt,)
+    f = np.empty_like(x)
+    p = MDParams((C.c_double * 3)(*[float(b) for b in box]), 1.0, dt, r_cut, skin, ftm2v, cap, 0)
+    st = MDStats()
+    en = np.empty((nsteps + 1, 2)) if want_energy else None
+    code = lib().or_md_run_multi(n, _pd(x), _pd(v), _pd(f), C.byref(p), nt, _pi(t), _pd(m),
+                                 ph.ptr, rh.ptr, em.ptr, int(nsteps), _pd(en), C.byref(st))
+    stats = dict(steps=st.steps, rebuilds=st.rebuilds, list_entries=st.list_entries,
+                 max_count=st.max_count, flags=st.flags)
+    return dict(x=x, v=v, f=f, energy=en, stats=stats, code=int(code))

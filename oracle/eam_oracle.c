@@ -18,6 +18,7 @@
  *     whole steps)
  *   - spline segment arithmetic x = alpha*s, k = int(x), t = x - k
  *                                                              Table "flopmodel", segment row
+ *   - several atom types: rho_{t_j}, F_{t_i}, phi_{t_i t_j}   Sec. II-A, after Eq. (potential)
  * Readings where the paper is silent: self term excluded from rho_i; strict
  * "<" for both cutoffs; natural-cubic per-segment tables; wrap-then-minimum-
  * image periodic boxes; cells of edge >= r_cut + skin with index
@@ -765,4 +766,233 @@ double or_fm_loss_grad(int32_t n_cfg, const int64_t *off, const double *x, const
   }
   free(loss_c);
   return err ? NAN : loss;
+}
+
+/* ------------------------------------------------------- several atom types */
+
+/* Multi-species EAM.  Sec. II-A lets the density, embedding and pair
+ * functions depend on the atoms' types (after Eq. potential):
+ *   rho_i  = sum_j rho_{t_j}(r_ij)     (the density an atom of type t_j emits)
+ *   U      = 1/2 sum_{i != j} phi_{t_i t_j}(r_ij) + sum_i F_{t_i}(rho_i)
+ *   -dU/dx_i = sum_j [F'_i rho'_{t_j}(r) + F'_j rho'_{t_i}(r) + phi'_{t_i t_j}(r)]
+ *              (x_j - x_i)/r                                  Eq. (EAMforce)
+ * Tables: rho[t] and emb[t] for t < nt, phi[a*nt + b] (the caller passes the
+ * same table for (a, b) and (b, a)); one mass per type.  With nt = 1 these
+ * reduce to the single-species functions above. */
+
+int32_t or_density_multi(int64_t n, const double *x, const double box[3], const int32_t *cnt,
+                         const int32_t *nbr, int32_t cap, double rc, int32_t nt,
+                         const int32_t *type, const or_spline *rho, const or_spline *emb,
+                         double *rho_out, double *fp_out) {
+  const double half[3] = {0.5 * box[0], 0.5 * box[1], 0.5 * box[2]};
+  const double rc2 = rc * rc;
+  int32_t flag = 0;
+  (void)nt;
+#pragma omp parallel for schedule(static) reduction(| : flag)
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0, d[3];
+    int32_t m = cnt[i] < cap ? cnt[i] : cap;
+    for (int32_t k = 0; k < m; ++k) {
+      int32_t j = nbr[i * cap + k];
+      double r2 = dist2(x + 3 * i, x + 3 * j, box, half, d);
+      if (r2 < rc2) acc += spl_f(&rho[type[j]], sqrt(r2));
+    }
+    const or_spline *F = &emb[type[i]];
+    rho_out[i] = acc;
+    if (fp_out) fp_out[i] = spl_df(F, acc);
+    if (acc > spl_end(F)) flag |= 1;
+  }
+  return flag;
+}
+
+void or_forces_multi(int64_t n, const double *x, const double box[3], const int32_t *cnt,
+                     const int32_t *nbr, int32_t cap, double rc, int32_t nt, const int32_t *type,
+                     const or_spline *phi, const or_spline *rho, const double *fp, double *f) {
+  const double half[3] = {0.5 * box[0], 0.5 * box[1], 0.5 * box[2]};
+  const double rc2 = rc * rc;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double fx = 0.0, fy = 0.0, fz = 0.0, d[3];
+    const int32_t ti = type[i];
+    int32_t m = cnt[i] < cap ? cnt[i] : cap;
+    for (int32_t k = 0; k < m; ++k) {
+      int32_t j = nbr[i * cap + k];
+      const int32_t tj = type[j];
+      double r2 = dist2(x + 3 * i, x + 3 * j, box, half, d);
+      if (r2 < rc2) {
+        double r = sqrt(r2);
+        double s = fp[i] * spl_df(&rho[tj], r) + fp[j] * spl_df(&rho[ti], r) +
+                   spl_df(&phi[ti * nt + tj], r);
+        fx += s * d[0] / r;
+        fy += s * d[1] / r;
+        fz += s * d[2] / r;
+      }
+    }
+    f[3 * i + 0] = fx;
+    f[3 * i + 1] = fy;
+    f[3 * i + 2] = fz;
+  }
+}
+
+/* Totals of Eq. (potential) and the kinetic energy, summed in atom order. */
+void or_energy_multi(int64_t n, const double *x, const double *v, const double box[3],
+                     const int32_t *cnt, const int32_t *nbr, int32_t cap, double rc, int32_t nt,
+                     const int32_t *type, const or_spline *phi, const or_spline *rho,
+                     const or_spline *emb, const double *mass, double ftm2v, double *pe,
+                     double *ke) {
+  const double half[3] = {0.5 * box[0], 0.5 * box[1], 0.5 * box[2]};
+  const double rc2 = rc * rc;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  double *rho_i = (double *)malloc(nn * sizeof(double));
+  double *ep = (double *)malloc(nn * sizeof(double));
+  double *ek = (double *)malloc(nn * sizeof(double));
+  or_density_multi(n, x, box, cnt, nbr, cap, rc, nt, type, rho, emb, rho_i, NULL);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double pair = 0.0, d[3];
+    const int32_t ti = type[i];
+    int32_t m = cnt[i] < cap ? cnt[i] : cap;
+    for (int32_t k = 0; k < m; ++k) {
+      int32_t j = nbr[i * cap + k];
+      double r2 = dist2(x + 3 * i, x + 3 * j, box, half, d);
+      if (r2 < rc2) pair += spl_f(&phi[ti * nt + type[j]], sqrt(r2));
+    }
+    ep[i] = 0.5 * pair + spl_f(&emb[ti], rho_i[i]);
+    if (v) {
+      const double *vi = v + 3 * i;
+      ek[i] = 0.5 * mass[ti] * ((vi[0] * vi[0] + vi[1] * vi[1]) + vi[2] * vi[2]) / ftm2v;
+    }
+  }
+  double sp = 0.0, sk = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    sp += ep[i];
+    if (v) sk += ek[i];
+  }
+  *pe = sp;
+  if (ke) *ke = sk;
+  free(rho_i);
+  free(ep);
+  free(ek);
+}
+
+static int forces_now_multi(int64_t n, const double *x, const or_md_params *p, int32_t nt,
+                            const int32_t *type, const or_spline *phi, const or_spline *rho,
+                            const or_spline *emb, md_scratch *w, double *f, or_md_stats *st) {
+  st->flags |= or_density_multi(n, x, p->box, w->cnt, w->nbr, p->cap, p->r_cut, nt, type, rho,
+                                emb, w->rho, w->fp);
+  or_forces_multi(n, x, p->box, w->cnt, w->nbr, p->cap, p->r_cut, nt, type, phi, rho, w->fp, f);
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!isfinite(f[i])) return OR_E_NONFINITE;
+  return OR_OK;
+}
+
+/* Velocity-Verlet as or_md_run, with the acceleration of atom i scaled by
+ * 1/mass[type[i]] (p->mass is not used). */
+int32_t or_md_run_multi(int64_t n, double *x, double *v, double *f, const or_md_params *p,
+                        int32_t nt, const int32_t *type, const double *mass, const or_spline *phi,
+                        const or_spline *rho, const or_spline *emb, int64_t nsteps,
+                        double *energy, or_md_stats *st) {
+  memset(st, 0, sizeof(*st));
+  int32_t nc[3];
+  double ic[3];
+  const double rl = p->r_cut + p->skin;
+  if (or_cell_grid(p->box, rl, nc, ic) != OR_OK &&
+      ((p->box[0] > 0.0 && p->box[0] < 2.0 * rl) || (p->box[1] > 0.0 && p->box[1] < 2.0 * rl) ||
+       (p->box[2] > 0.0 && p->box[2] < 2.0 * rl)))
+    return OR_E_BOX;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  md_scratch w;
+  w.cnt = (int32_t *)malloc(nn * sizeof(int32_t));
+  w.nbr = (int32_t *)malloc(nn * (size_t)p->cap * sizeof(int32_t));
+  w.xref = (double *)malloc(nn * 3 * sizeof(double));
+  w.rho = (double *)malloc(nn * sizeof(double));
+  w.fp = (double *)malloc(nn * sizeof(double));
+  const double half[3] = {0.5 * p->box[0], 0.5 * p->box[1], 0.5 * p->box[2]};
+  const double lim2 = 0.25 * p->skin * p->skin;
+  const double hdt = 0.5 * p->dt;
+  int rc = OR_OK;
+
+  if (or_wrap(n, x, p->box)) rc = OR_E_LOST;
+  if (rc == OR_OK) rc = build_list(n, x, p, &w, st);
+  if (rc == OR_OK) rc = forces_now_multi(n, x, p, nt, type, phi, rho, emb, &w, f, st);
+  if (rc == OR_OK && energy)
+    or_energy_multi(n, x, v, p->box, w.cnt, w.nbr, p->cap, p->r_cut, nt, type, phi, rho, emb,
+                    mass, p->ftm2v, &energy[0], &energy[1]);
+  for (int64_t s = 0; s < nsteps && rc == OR_OK; ++s) {
+    for (int64_t i = 0; i < n; ++i) {
+      const double acc = p->ftm2v / mass[type[i]];
+      for (int d = 0; d < 3; ++d) {
+        v[3 * i + d] += hdt * (f[3 * i + d] * acc);
+        x[3 * i + d] += p->dt * v[3 * i + d];
+      }
+    }
+    if (or_wrap(n, x, p->box)) {
+      rc = OR_E_LOST;
+      break;
+    }
+    double mx2 = 0.0, d[3];
+    for (int64_t i = 0; i < n; ++i) {
+      double r2 = dist2(w.xref + 3 * i, x + 3 * i, p->box, half, d);
+      if (r2 > mx2) mx2 = r2;
+    }
+    if (mx2 > lim2) {
+      rc = build_list(n, x, p, &w, st);
+      st->rebuilds++;
+      if (rc != OR_OK) break;
+    }
+    rc = forces_now_multi(n, x, p, nt, type, phi, rho, emb, &w, f, st);
+    if (rc != OR_OK) break;
+    for (int64_t i = 0; i < n; ++i) {
+      const double acc = p->ftm2v / mass[type[i]];
+      for (int d = 0; d < 3; ++d) v[3 * i + d] += hdt * (f[3 * i + d] * acc);
+    }
+    st->steps++;
+    if (energy)
+      or_energy_multi(n, x, v, p->box, w.cnt, w.nbr, p->cap, p->r_cut, nt, type, phi, rho, emb,
+                      mass, p->ftm2v, &energy[2 * (s + 1)], &energy[2 * (s + 1) + 1]);
+  }
+  free(w.cnt);
+  free(w.nbr);
+  free(w.xref);
+  free(w.rho);
+  free(w.fp);
+  return rc;
+}
+
+/* Forces, rho, F' and potential energy of a configuration from scratch. */
+int32_t or_forces_at_multi(int64_t n, const double *x_in, const double box[3], double rc,
+                           double skin, int32_t cap, int32_t nt, const int32_t *type,
+                           const or_spline *phi, const or_spline *rho, const or_spline *emb,
+                           double *f, double *rho_out, double *fp_out, double *pe) {
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  double *x = (double *)malloc(nn * 3 * sizeof(double));
+  memcpy(x, x_in, (size_t)n * 3 * sizeof(double));
+  int32_t rcode = OR_OK;
+  if (or_wrap(n, x, box)) rcode = OR_E_LOST;
+  int32_t *cnt = (int32_t *)malloc(nn * sizeof(int32_t));
+  int32_t *nbr = (int32_t *)malloc(nn * (size_t)cap * sizeof(int32_t));
+  double *fp = (double *)malloc(nn * sizeof(double));
+  double *rh = (double *)malloc(nn * sizeof(double));
+  if (rcode == OR_OK) {
+    int32_t mx = or_list_cells(n, x, box, rc + skin, cap, cnt, nbr);
+    if (mx > cap) rcode = OR_E_OVERFLOW;
+  }
+  if (rcode == OR_OK) {
+    int32_t fl = or_density_multi(n, x, box, cnt, nbr, cap, rc, nt, type, rho, emb, rh, fp);
+    or_forces_multi(n, x, box, cnt, nbr, cap, rc, nt, type, phi, rho, fp, f);
+    if (pe) {
+      double one[8] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+      or_energy_multi(n, x, NULL, box, cnt, nbr, cap, rc, nt, type, phi, rho, emb, one, 1.0, pe,
+                      NULL);
+    }
+    if (rho_out) memcpy(rho_out, rh, (size_t)n * sizeof(double));
+    if (fp_out) memcpy(fp_out, fp, (size_t)n * sizeof(double));
+    rcode = fl;
+  }
+  free(x);
+  free(cnt);
+  free(nbr);
+  free(fp);
+  free(rh);
+  return rcode;
 }

@@ -35,3 +35,19 @@ def test_batch_recipe():
         assert 5 <= n <= 20
         assert 2 * n ** 3 - int(0.02 * 2 * n ** 3) <= r.n <= 2 * n ** 3
         assert 300.0 <= r.temperature <= 2000.0
+
+
+def test_alloy_box_recipe():
+    from workloads import configs, potential as P
+
+    b = configs.alloy_box(6, 5, temperature=900.0)
+    assert b.types.dtype == np.int32 and set(np.unique(b.types)) == {0, 1}
+    assert abs(b.types.mean() - 0.5) < 0.1
+    m = np.asarray(P.ALLOY_MASS)[b.types]
+    assert np.all(np.abs((m[:, None] * b.v).sum(axis=0)) < 1e-10)
+    ke = 0.5 * np.sum(m[:, None] * b.v ** 2) / configs.FTM2V
+    assert abs(ke - 0.5 * (3 * b.n - 3) * configs.KBOLTZ * 900.0) < 1e-9 * ke
+    assert np.all((b.x >= 0) & (b.x < b.box))
+    # the alloy tables: phi[a][b] is phi[b][a], one table per type for rho and F
+    phi, rho, emb = P.alloy_tables(n_knots=50)
+    assert phi[0][1] is phi[1][0] and len(rho) == len(emb) == 2

@@ -35,6 +35,7 @@ class Box:
     n_cells: int  # lattice cells per edge
     temperature: float
     site_ids: np.ndarray  # (N,) int64 lattice site id of each atom
+    types: np.ndarray = None  # (N,) int32 atom types of a multi-species box, else None
 
     @property
     def n(self) -> int:
@@ -174,3 +175,38 @@ def config_slab_801792() -> Box:
     """The paper's benchmark slab shape: 256 x 261 x 6 BCC cells = 801,792 atoms,
     open in x and y, 300 K, seed 6."""
     return slab(256, 261, 6, 6)
+
+
+# --- random substitutional binary alloy ---------------------------------------
+
+def maxwell_boltzmann_masses(rng: np.random.Generator, mass: np.ndarray,
+                             temperature: float) -> np.ndarray:
+    """Velocities for per-atom masses: zero net momentum, KE = (3N-3)/2 kB T exactly."""
+    mass = np.asarray(mass, dtype=np.float64)
+    n = mass.shape[0]
+    v = np.sqrt(KBOLTZ * temperature * FTM2V / mass)[:, None] * rng.standard_normal((n, 3))
+    if temperature <= 0.0 or n < 2:
+        return np.zeros_like(v)
+    v -= (mass[:, None] * v).sum(axis=0) / mass.sum()
+    ke = 0.5 * np.sum(mass[:, None] * v * v) / FTM2V
+    return v * np.sqrt(0.5 * (3 * n - 3) * KBOLTZ * temperature / ke)
+
+
+def alloy_box(n_cells: int, seed: int, *, frac_1: float = 0.5, masses=(180.95, 95.95),
+              sigma_x: float = 0.01, temperature: float = 300.0, a: float = A_LAT) -> Box:
+    """BCC box whose sites hold type 1 with probability frac_1, else type 0.
+    Draw order: displacements, types, velocities."""
+    rng = np.random.default_rng(seed)
+    sites = bcc_sites(n_cells, a)
+    x = sites + sigma_x * rng.standard_normal(sites.shape)
+    box = np.full(3, n_cells * a)
+    x = wrap_into_box(x, box)
+    types = (rng.random(x.shape[0]) < frac_1).astype(np.int32)
+    v = maxwell_boltzmann_masses(rng, np.asarray(masses)[types], temperature)
+    return Box(x=x, v=v, box=box, n_cells=n_cells, temperature=temperature,
+               site_ids=np.arange(x.shape[0], dtype=np.int64), types=types)
+
+
+def config_alloy_128k() -> Box:
+    """128,000-atom random equiatomic binary BCC alloy (40^3 cells), 300 K, seed 7."""
+    return alloy_box(40, 7)

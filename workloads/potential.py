@@ -205,3 +205,65 @@ def fm_tables(seed: int = 55):
     for x1, y in fm_knot_values(seed):
         tabs.append(natural_spline_from_values(0.0, x1 / (FM_KNOTS - 1), y))
     return tuple(tabs)
+
+
+# --- a synthetic binary alloy (several atom types) -----------------------------
+#
+# Type 0 is the specified potential's species; type 1 is a lighter species with
+# a shorter length scale and a weaker density.  Pairs (a, b) use the mean of the
+# two length scales:
+#     rho_t(r)   = S_t exp(-6 (r/r0_t - 1)) fc(r)
+#     F_t(rho)   = -E_t sqrt(rho)
+#     phi_ab(r)  = 0.3 exp(-8 (r/r0_ab - 1)) fc(r),   r0_ab = (r0_a + r0_b)/2
+
+ALLOY_R0 = (R0, 2.72)
+ALLOY_RHO_S = (1.0, 0.8)
+ALLOY_EMB_A = (EMB_A, 2.4)
+ALLOY_MASS = (180.95, 95.95)
+
+
+def alloy_r0(a: int, b: int) -> float:
+    return 0.5 * (ALLOY_R0[a] + ALLOY_R0[b])
+
+
+def alloy_phi(r, a, b):
+    return PHI_A * np.exp(-PHI_B * (np.asarray(r, dtype=np.float64) / alloy_r0(a, b) - 1.0)) * fc(r)
+
+
+def alloy_dphi(r, a, b):
+    r = np.asarray(r, dtype=np.float64)
+    r0 = alloy_r0(a, b)
+    e = PHI_A * np.exp(-PHI_B * (r / r0 - 1.0))
+    return e * (-PHI_B / r0) * fc(r) + e * dfc(r)
+
+
+def alloy_rho(r, t):
+    r = np.asarray(r, dtype=np.float64)
+    return ALLOY_RHO_S[t] * np.exp(-RHO_B * (r / ALLOY_R0[t] - 1.0)) * fc(r)
+
+
+def alloy_drho(r, t):
+    r = np.asarray(r, dtype=np.float64)
+    e = ALLOY_RHO_S[t] * np.exp(-RHO_B * (r / ALLOY_R0[t] - 1.0))
+    return e * (-RHO_B / ALLOY_R0[t]) * fc(r) + e * dfc(r)
+
+
+def alloy_emb(x, t):
+    return -ALLOY_EMB_A[t] * np.sqrt(np.asarray(x, dtype=np.float64))
+
+
+def alloy_demb(x, t):
+    return -0.5 * ALLOY_EMB_A[t] / np.sqrt(np.asarray(x, dtype=np.float64))
+
+
+def alloy_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX):
+    """(phi[a][b], rho[t], F[t]) tables of the binary alloy: phi, rho on [0, rc],
+    F on [0, rho_max]; phi[a][b] and phi[b][a] are the same table."""
+    nt = len(ALLOY_R0)
+    phi_t = [[None] * nt for _ in range(nt)]
+    for a in range(nt):
+        for b in range(a, nt):
+            phi_t[a][b] = phi_t[b][a] = tabulate(lambda r, a=a, b=b: alloy_phi(r, a, b), RC, n_knots)
+    rho_t = [tabulate(lambda r, t=t: alloy_rho(r, t), RC, n_knots) for t in range(nt)]
+    emb_t = [tabulate(lambda x, t=t: alloy_emb(x, t), rho_max, n_knots) for t in range(nt)]
+    return phi_t, rho_t, emb_t
