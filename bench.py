@@ -242,6 +242,34 @@ def bench_half(torch, md, configs, tabs, steps):
     return out
 
 
+def bench_alloy(torch, md, configs, potential, steps):
+    """Several atom types: the 128,000-atom random equiatomic binary alloy (per-type
+    rho and F, per-pair phi, per-type masses), same schedule as the main workload."""
+    box = configs.config_alloy_128k()
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+                       ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
+                       nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY, n_types=2)
+    s = md.System(p, potential.alloy_tables(), [box.n], box.box[None, :],
+                  masses=potential.ALLOY_MASS)
+    s.set_state(box.x, box.v)
+    s.set_types(box.types)
+    s.build_neighbors()
+    lpa, _ = s.autotune(20)
+    s.step(100)
+    st0 = s.stats()
+    sec, _ = time_steps(torch, s, steps)
+    st1 = s.stats()
+    dens = time_kernel(torch, s, md, md.PASS_DENSITY, 50)
+    frc = time_kernel(torch, s, md, md.PASS_FORCE_RAW, 50)
+    s.close()
+    return {"workload": "random equiatomic binary BCC alloy, 40^3 cells, 300 K",
+            "n_atoms": box.n, "n_types": 2, "steps": steps, "lanes_per_atom": lpa,
+            "timesteps_per_s": round(steps / sec, 1),
+            "density_pass_us": round(dens, 3), "force_pass_us": round(frc, 3),
+            "rebuilds": int(st1["rebuilds"] - st0["rebuilds"]),
+            "mean_list_length": round(st1["list_entries"] / box.n, 3)}
+
+
 def perf_model(torch, md, configs, tabs, steps: int = 1000):
     """Linear model of the step time at fixed N, t = A n_l + B n_int + C (the
     paper's Eq. linearmodel / Table "regression", with list entries standing
@@ -507,6 +535,8 @@ def main() -> int:
         log(f"  slab: {out['secondary_slab_801792']}")
         out["secondary_half_list_128k"] = bench_half(torch, md, configs, tabs, 5000)
         log(f"  half list: {out['secondary_half_list_128k']}")
+        out["secondary_alloy_128k"] = bench_alloy(torch, md, configs, potential, 5000)
+        log(f"  binary alloy: {out['secondary_alloy_128k']}")
         out["secondary_stable_128k"] = bench_stable(torch, md, configs, potential, 5000)
         log(f"  stable-lattice context: {out['secondary_stable_128k']}")
         out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)

@@ -76,6 +76,9 @@ typedef int32_t md_status;
 #define MD_LIST_FULL 0
 #define MD_LIST_HALF 1
 
+/* Most atom types of the multi-species form. */
+#define MD_MAX_TYPES 4
+
 /* A cubic spline on equally spaced knots x0 + k/inv_dx, k = 0..n_knots-1.
  * coef (host) holds (n_knots-1) rows of 4 float64: segment k evaluates
  * c0 + c1 t + c2 t^2 + c3 t^3 with t = (s - x0) inv_dx - k in [0,1); the
@@ -105,7 +108,8 @@ typedef struct md_params {
   int32_t lanes_per_atom;/* 0 = automatic, else 1, 2, 4 or 8 lanes per atom */
   int32_t sort_every;    /* re-sort atoms by cell every this many chunks (0 = never) */
   int32_t list_mode;     /* MD_LIST_FULL or MD_LIST_HALF */
-  int32_t reserved;      /* 0 */
+  int32_t n_types;       /* atom types: 0 or 1 (one species, md_create), or
+                            2..MD_MAX_TYPES (md_create_multi) */
 } md_params;
 
 typedef struct md_ctx md_ctx;
@@ -144,6 +148,31 @@ md_status md_workspace_size(const md_params* p, int32_t n_rep, const int64_t* re
 md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
                     const double* rep_box, const md_spline* phi, const md_spline* rho,
                     const md_spline* emb, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Multi-species EAM (paper Sec. II-A: the density, embedding and pair
+ * functions depend on the atom types, after Eq. potential):
+ *   rho_i = sum_j rho_{t_j}(r_ij), U = 1/2 sum phi_{t_i t_j} + sum_i F_{t_i}(rho_i),
+ *   F_i = sum_j [F'_i rho'_{t_j} + F'_j rho'_{t_i} + phi'_{t_i t_j}] (x_j - x_i)/r.
+ * p->n_types = T in 2..MD_MAX_TYPES; float64 (MD_FP64) and the full list only.
+ * Host arrays: phi[a*T + b] (the table of pair types a, b; phi[b*T + a] must
+ * hold the same coefficients), rho[t] (the density an atom of type t emits),
+ * emb[t] (F of type t), masses[t] (amu; p->mass is not used).  Every rho and
+ * phi table shares rho[0]'s knot grid (x0 = 0, reaching r_cut); every F table
+ * shares emb[0]'s.  Returns MD_E_TABLE for mismatched grids or an asymmetric
+ * phi, MD_E_ARG for a bad count or mass.  All atoms are type 0 until
+ * md_set_types.  The workspace size comes from md_workspace_size with the
+ * same p. */
+md_status md_create_multi(md_ctx** out, const md_params* p, int32_t n_rep,
+                          const int64_t* rep_atoms, const double* rep_box, const md_spline* phi,
+                          const md_spline* rho, const md_spline* emb, const double* masses,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Types of the atoms (device, [n] int32, original order, each in [0, T)) of a
+ * context made by md_create_multi.  Returns MD_E_ARG if any type is out of
+ * range (those atoms become type 0) or if the context has one species.
+ * Forces belong to the old types afterwards:
+ * md_build_neighbors must follow before md_step. */
+md_status md_set_types(md_ctx* ctx, const int32_t* type);
 
 /* Upload positions x and on-step velocities v (device, [n][3] float64,
  * original order).  Positions are wrapped into the box along periodic

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdeam.so")
-SOURCES = ["md_kernels.hip", "md_half.hip", "md_api.hip", "md_fm.hip"]
+SOURCES = ["md_kernels.hip", "md_half.hip", "md_multi.hip", "md_api.hip", "md_fm.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -56,6 +56,9 @@ md_status check_params(const md_params* p) {
   if (p->list_mode != MD_LIST_FULL && p->list_mode != MD_LIST_HALF) return MD_E_ARG;
   // the half-list passes exist in float64 only
   if (p->list_mode == MD_LIST_HALF && p->precision != MD_FP64) return MD_E_ARG;
+  // several atom types: float64, full list
+  if (p->n_types < 0 || p->n_types > kMaxTypes) return MD_E_ARG;
+  if (p->n_types > 1 && (p->precision != MD_FP64 || p->list_mode != MD_LIST_FULL)) return MD_E_ARG;
   return MD_OK;
 }
 
@@ -117,6 +120,8 @@ struct md_ctx {
   int cur = 0;
   int lpa = 1;
   bool half = false;    // half-list pair passes
+  bool multi = false;   // several atom types
+  MultiTables mt{};
   bool has_state = false;
   bool built = false;
   bool v_half = false;  // velocities are half-step (after build)
@@ -175,12 +180,29 @@ struct Buffers {
   int32_t* sort_id;
   double4 *snap_pos, *snap_vel;
   double *partial, *energy;
+  // multi-species form only
+  double4 *m_rho_seg, *m_phi_val, *m_rho_val, *m_emb_val;
+  double* m_frow;
+  uint8_t *type, *type_orig, *sort_type;
   // half-list form only
   uint32_t *hnbr, *rslot_u, *rslot;
   int32_t *hcnt, *rcnt, *rfill;
   double *pval, *own_rho;
   double4 *qval, *own_f;
 };
+
+// Doubles per segment of the interleaved force rows: 3 per rho'_t and per
+// unordered pair phi'_ab, rounded up to a 128-byte line.
+int multi_seg_stride(int nt) {
+  const int rows = nt + nt * (nt + 1) / 2;
+  return (3 * rows + 15) / 16 * 16;
+}
+
+// Row of phi'_ab (a, b in any order) within a segment of the force rows.
+int multi_pair_row(int nt, int a, int b) {
+  if (a > b) std::swap(a, b);
+  return nt + a * nt - a * (a - 1) / 2 + (b - a);
+}
 
 size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s, int nr, int ne,
              Buffers* b) {
@@ -223,6 +245,20 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.snap_vel = c.take<double4>(N);
   o.partial = c.take<double>(2 * s.atile_blocks);
   o.energy = c.take<double>(2 * (size_t)n_rep);
+  o.m_rho_seg = o.m_phi_val = o.m_rho_val = o.m_emb_val = nullptr;
+  o.m_frow = nullptr;
+  o.type = o.type_orig = o.sort_type = nullptr;
+  if (p->n_types > 1) {
+    const size_t T = (size_t)p->n_types;
+    o.m_rho_seg = c.take<double4>(T * (nr - 1));
+    o.m_frow = c.take<double>((size_t)multi_seg_stride((int)T) * (nr - 1));
+    o.m_phi_val = c.take<double4>(T * T * (nr - 1));
+    o.m_rho_val = c.take<double4>(T * (nr - 1));
+    o.m_emb_val = c.take<double4>(T * (ne - 1));
+    o.type = c.take<uint8_t>(N);
+    o.type_orig = c.take<uint8_t>(N);
+    o.sort_type = c.take<uint8_t>(N);
+  }
   o.hnbr = o.rslot_u = o.rslot = nullptr;
   o.hcnt = o.rcnt = o.rfill = nullptr;
   o.pval = o.own_rho = nullptr;
@@ -296,6 +332,9 @@ md_status status_code(int32_t bits) {
 // rebuild in this step (the half form re-derives its half list then).
 hipError_t density_pass(md_ctx* c, const State& s, int lpa, const double4* pos,
                         const int32_t* cond, int32_t* clear_flag, int32_t* rclear, bool want_rho) {
+  if (c->multi)
+    return launch_multi_density(c->L, c->g, s, c->mt, lpa, pos, cond, clear_flag, rclear,
+                                c->sz.cells, want_rho);
   if (c->half)
     return launch_half_density(c->L, c->g, s, c->t, pos, cond, false, clear_flag, rclear,
                                c->sz.cells, want_rho);
@@ -305,6 +344,9 @@ hipError_t density_pass(md_ctx* c, const State& s, int lpa, const double4* pos,
 
 hipError_t force_integrate_pass(md_ctx* c, const State& s, int lpa, const double4* pos_in,
                                 double4* pos_out, int32_t* flag_next, int32_t* rflag_next) {
+  if (c->multi)
+    return launch_multi_force_integrate(c->L, c->g, s, c->mt, lpa, pos_in, pos_out, flag_next,
+                                        rflag_next);
   if (c->half)
     return launch_half_force_integrate(c->L, c->g, s, c->t, pos_in, pos_out, flag_next,
                                        rflag_next);
@@ -313,6 +355,7 @@ hipError_t force_integrate_pass(md_ctx* c, const State& s, int lpa, const double
 }
 
 hipError_t force_only_pass(md_ctx* c, const State& s, const double4* pos) {
+  if (c->multi) return launch_multi_force_only(c->L, c->g, s, c->mt, c->lpa, pos);
   if (c->half) return launch_half_force_only(c->L, c->g, s, c->t, pos);
   return launch_force_only(c->L, c->g, s, c->t, c->p.precision, c->lpa, pos);
 }
@@ -472,9 +515,61 @@ md_status md_workspace_size(const md_params* p, int32_t n_rep, const int64_t* re
   return MD_OK;
 }
 
-md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
-                    const double* rep_box, const md_spline* phi, const md_spline* rho,
-                    const md_spline* emb, void* workspace, size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Tables and masses of the multi-species form (validated by md_create_multi).
+struct MultiIn {
+  int32_t nt;
+  const md_spline* phi;  // [nt * nt]
+  const md_spline* rho;  // [nt]
+  const md_spline* emb;  // [nt]
+  const double* masses;  // [nt]
+};
+
+void multi_tables(const MultiIn& mi, std::vector<double4>* rseg, std::vector<double>* frow,
+                  std::vector<double4>* pv, std::vector<double4>* rv, std::vector<double4>* ev) {
+  const int nt = mi.nt;
+  const int ns = mi.rho[0].n_knots - 1;
+  const double a = mi.rho[0].inv_dx;
+  const int S = multi_seg_stride(nt);
+  auto value_rows = [&](const md_spline& sp, std::vector<double4>* out) {
+    for (int k = 0; k < sp.n_knots - 1; ++k) {
+      const double* c = sp.coef + 4 * (size_t)k;
+      out->push_back(make_double4(c[0], c[1], c[2], c[3]));
+    }
+  };
+  // derivative quadratic in t, pre-scaled by alpha: f'(t) = (c1 + 2 c2 t + 3 c3 t^2) alpha
+  auto slope_row = [&](const md_spline& sp, int k, double* dst) {
+    const double* c = sp.coef + 4 * (size_t)k;
+    dst[0] = c[1] * a;
+    dst[1] = 2.0 * c[2] * a;
+    dst[2] = 3.0 * c[3] * a;
+  };
+  rseg->resize((size_t)ns * nt);
+  frow->assign((size_t)ns * S, 0.0);
+  for (int k = 0; k < ns; ++k) {
+    double* seg = frow->data() + (size_t)k * S;
+    for (int t = 0; t < nt; ++t) {
+      const double* c = mi.rho[t].coef + 4 * (size_t)k;
+      (*rseg)[(size_t)k * nt + t] = make_double4(c[0], c[1], c[2], c[3]);
+      slope_row(mi.rho[t], k, seg + 3 * t);
+    }
+    for (int p = 0; p < nt; ++p)
+      for (int q = p; q < nt; ++q) slope_row(mi.phi[p * nt + q], k, seg + 3 * multi_pair_row(nt, p, q));
+  }
+  for (int t = 0; t < nt; ++t) {
+    value_rows(mi.rho[t], rv);
+    value_rows(mi.emb[t], ev);
+  }
+  for (int q = 0; q < nt * nt; ++q) value_rows(mi.phi[q], pv);
+}
+
+md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                      const double* rep_box, const md_spline* phi, const md_spline* rho,
+                      const md_spline* emb, const MultiIn* mi, void* workspace,
+                      size_t workspace_bytes, void* stream) {
   if (!out) return MD_E_ARG;
   *out = nullptr;
   md_status s = check_params(p);
@@ -561,6 +656,16 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   UP(b.rho_val32, rv32);
   UP(b.dpair_a32, da32);
   UP(b.dpair_b32, db32);
+  if (mi) {
+    std::vector<double4> mrs, mpv, mrv, mev;
+    std::vector<double> mfr;
+    multi_tables(*mi, &mrs, &mfr, &mpv, &mrv, &mev);
+    UP(b.m_rho_seg, mrs);
+    UP(b.m_frow, mfr);
+    UP(b.m_phi_val, mpv);
+    UP(b.m_rho_val, mrv);
+    UP(b.m_emb_val, mev);
+  }
 #undef UP
   hipError_t e = hipMemset(b.status, 0, SW_WORDS * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.bin_cnt, 0, (size_t)ls.cells * sizeof(int32_t));
@@ -569,6 +674,8 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   if (e == hipSuccess) e = hipMemset(b.cell_stat, 0, 3 * (size_t)ls.cells * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b.frc, 0, (size_t)ls.n * sizeof(double4));
   if (e == hipSuccess && b.rfill) e = hipMemset(b.rfill, 0, (size_t)ls.n * sizeof(int32_t));
+  if (e == hipSuccess && b.type) e = hipMemset(b.type, 0, (size_t)ls.n);
+  if (e == hipSuccess && b.type_orig) e = hipMemset(b.type_orig, 0, (size_t)ls.n);
   if (e == hipSuccess && b.hcnt) e = hipMemset(b.hcnt, 0, (size_t)ls.n * sizeof(int32_t));
   if (e == hipSuccess && b.rcnt) e = hipMemset(b.rcnt, 0, (size_t)ls.n * sizeof(int32_t));
   if (e != hipSuccess) {
@@ -592,6 +699,9 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   g.lim2 = 0.25 * p->skin * p->skin;
   g.dt = p->dt;
   g.acc = p->ftm2v / p->mass;
+  for (int q = 0; q < kMaxTypes; ++q) g.acc_t[q] = g.acc;
+  if (mi)
+    for (int q = 0; q < mi->nt; ++q) g.acc_t[q] = p->ftm2v / mi->masses[q];
   g.rc2f = (float)g.rc2;
 
   Tables& t = c->t;
@@ -667,6 +777,35 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   base.own_rho = b.own_rho;
   base.own_f = b.own_f;
   c->half = (p->list_mode == MD_LIST_HALF);
+  base.type = b.type;
+  base.type_orig = b.type_orig;
+  base.sort_type = b.sort_type;
+  if (mi) {
+    c->multi = true;
+    MultiTables& m = c->mt;
+    m.rho_seg = b.m_rho_seg;
+    m.frow = b.m_frow;
+    m.phi_val = b.m_phi_val;
+    m.rho_val = b.m_rho_val;
+    m.emb_val = b.m_emb_val;
+    m.seg_stride = multi_seg_stride(mi->nt);
+    m.lds_seg0 = multi_force_lds_seg0(mi->rho[0].n_knots, mi->nt);
+    for (int q = 0; q < kMaxTypes * kMaxTypes; ++q) m.pair_row[q] = 0;
+    for (int p = 0; p < mi->nt; ++p)
+      for (int q = 0; q < mi->nt; ++q) m.pair_row[p * mi->nt + q] = multi_pair_row(mi->nt, p, q);
+    m.r_inv_dx = mi->rho[0].inv_dx;
+    m.e_x0 = mi->emb[0].x0;
+    m.e_inv_dx = mi->emb[0].inv_dx;
+    m.nr = mi->rho[0].n_knots;
+    m.ne = mi->emb[0].n_knots;
+    m.n_types = mi->nt;
+    hipError_t e3 = allow_multi_lds(m);
+    if (e3 != hipSuccess) {
+      md_status r_ = hip_fail(c, e3, "hipFuncSetAttribute");
+      delete c;
+      return r_;
+    }
+  }
   c->st[0] = base;
   c->st[1] = base;
   c->st[0].pos = b.pos0;
@@ -681,6 +820,70 @@ md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64
   c->status = b.status;
   *out = c;
   return MD_OK;
+}
+
+bool same_coef(const md_spline& a, const md_spline& b) {
+  return a.n_knots == b.n_knots && a.x0 == b.x0 && a.inv_dx == b.inv_dx &&
+         std::memcmp(a.coef, b.coef, 4 * sizeof(double) * (size_t)(a.n_knots - 1)) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_create(md_ctx** out, const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                    const double* rep_box, const md_spline* phi, const md_spline* rho,
+                    const md_spline* emb, void* workspace, size_t workspace_bytes, void* stream) {
+  if (p && p->n_types > 1) return MD_E_ARG;  // several types: md_create_multi
+  return create_impl(out, p, n_rep, rep_atoms, rep_box, phi, rho, emb, nullptr, workspace,
+                     workspace_bytes, stream);
+}
+
+md_status md_create_multi(md_ctx** out, const md_params* p, int32_t n_rep,
+                          const int64_t* rep_atoms, const double* rep_box, const md_spline* phi,
+                          const md_spline* rho, const md_spline* emb, const double* masses,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return MD_E_ARG;
+  *out = nullptr;
+  if (!p || p->n_types < 2 || p->n_types > kMaxTypes || !phi || !rho || !emb || !masses)
+    return MD_E_ARG;
+  const int nt = p->n_types;
+  for (int t = 0; t < nt; ++t)
+    if (!(masses[t] > 0.0) || !std::isfinite(masses[t])) return MD_E_ARG;
+  // every rho and phi table on the grid of rho[0], every F table on the grid of emb[0]
+  for (int q = 0; q < nt * nt; ++q) {
+    if (!valid_spline(&phi[q])) return MD_E_TABLE;
+    if (phi[q].n_knots != rho[0].n_knots || phi[q].inv_dx != rho[0].inv_dx || phi[q].x0 != 0.0)
+      return MD_E_TABLE;
+  }
+  for (int t = 0; t < nt; ++t) {
+    if (!valid_spline(&rho[t]) || !valid_spline(&emb[t])) return MD_E_TABLE;
+    if (rho[t].n_knots != rho[0].n_knots || rho[t].inv_dx != rho[0].inv_dx || rho[t].x0 != 0.0)
+      return MD_E_TABLE;
+    if (emb[t].n_knots != emb[0].n_knots || emb[t].inv_dx != emb[0].inv_dx ||
+        emb[t].x0 != emb[0].x0)
+      return MD_E_TABLE;
+  }
+  // phi_ab and phi_ba must be one function (else no energy is conserved)
+  for (int a = 0; a < nt; ++a)
+    for (int b = a + 1; b < nt; ++b)
+      if (!same_coef(phi[a * nt + b], phi[b * nt + a])) return MD_E_TABLE;
+  const MultiIn mi{nt, phi, rho, emb, masses};
+  return create_impl(out, p, n_rep, rep_atoms, rep_box, &phi[0], &rho[0], &emb[0], &mi, workspace,
+                     workspace_bytes, stream);
+}
+
+md_status md_set_types(md_ctx* c, const int32_t* type) {
+  if (!c || !type) return MD_E_ARG;
+  if (!c->multi) return MD_E_ARG;
+  HIPC(c, hipMemsetAsync(c->status + SW_TYPE_CHECK, 0, sizeof(int32_t), c->L.stream));
+  HIPC(c, launch_set_types(c->L, c->g, c->st[c->cur], type, c->mt.n_types, c->has_state));
+  int32_t w[SW_WORDS];
+  md_status s = read_status(c, w);
+  if (s != MD_OK) return s;
+  // forces and the half-step velocities belong to the old types
+  c->built = false;
+  return w[SW_TYPE_CHECK] ? MD_E_ARG : MD_OK;
 }
 
 md_status md_set_state(md_ctx* c, const double* x, const double* v) {
@@ -704,7 +907,7 @@ md_status md_build_neighbors(md_ctx* c) {
   if (s != MD_OK) return s;
   if ((s = forces_now(c, false)) != MD_OK) return s;
   if (!c->v_half) {
-    HIPC(c, launch_halfkick(c->L, c->g, c->st[c->cur], -0.5 * c->p.dt * c->g.acc));
+    HIPC(c, launch_halfkick(c->L, c->g, c->st[c->cur], -0.5 * c->p.dt));
     c->v_half = true;
   }
   c->chunks_since_sort = 0;
@@ -770,7 +973,10 @@ md_status md_energy(md_ctx* c, double* pe, double* ke) {
     // velocities are on-step: no half-kick correction
     g.dt = 0.0;
   }
-  HIPC(c, launch_energy(c->L, g, st, c->t, c->energy_dev, c->n_rep));
+  if (c->multi)
+    HIPC(c, launch_multi_energy(c->L, g, st, c->mt, c->energy_dev, c->n_rep));
+  else
+    HIPC(c, launch_energy(c->L, g, st, c->t, c->energy_dev, c->n_rep));
   std::vector<double> h(2 * (size_t)c->n_rep);
   HIPC(c, hipMemcpyAsync(h.data(), c->energy_dev, h.size() * sizeof(double),
                          hipMemcpyDeviceToHost, c->L.stream));
@@ -793,8 +999,8 @@ md_status md_get_state(md_ctx* c, double* x, double* v, double* f) {
   } else if (f) {
     return MD_E_ORDER;
   }
-  const double vscale = c->v_half ? 0.5 * c->p.dt * c->g.acc : 0.0;
-  HIPC(c, launch_export(c->L, c->g, c->st[c->cur], x, v, f, nullptr, nullptr, vscale));
+  const double coef = c->v_half ? 0.5 * c->p.dt : 0.0;
+  HIPC(c, launch_export(c->L, c->g, c->st[c->cur], x, v, f, nullptr, nullptr, coef));
   HIPC(c, hipStreamSynchronize(c->L.stream));
   return MD_OK;
 }

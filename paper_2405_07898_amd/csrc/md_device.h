@@ -54,6 +54,11 @@ __device__ __forceinline__ unsigned long long* counter64(int32_t* status, int wo
   return reinterpret_cast<unsigned long long*>(status + word);
 }
 
+// ftm2v / mass of the atom in slot i (per type in the multi-species form).
+__device__ __forceinline__ double acc_of(const Geometry& g, const State& s, int64_t i) {
+  return s.type ? g.acc_t[s.type[i]] : g.acc;
+}
+
 // Image shift encoded in a list entry: 2 bits per dimension, value s+1 for a
 // shift of s box lengths (s in -1, 0, +1) added to x_j - x_i.
 __device__ __forceinline__ void apply_shift(uint32_t code, const RepDev& rp, double& dx, double& dy,
@@ -126,6 +131,36 @@ __device__ __forceinline__ void separation(uint32_t e, const RepDev& rp, double 
   dz = qz - pz;
   const uint32_t code = e >> kIndexBits;
   if (code != kNoShift) apply_shift(code, rp, dx, dy, dz);
+}
+
+// Sum over the LPA lanes of one atom, combined in a lane-symmetric order so
+// every lane ends with the same bits.
+template <int LPA>
+__device__ __forceinline__ double lane_sum_sym(double v) {
+#pragma unroll
+  for (int o = 1; o < LPA; o <<= 1) {
+    const double w = __shfl_xor(v, o, 64);
+    v = ((threadIdx.x & o) == 0) ? v + w : w + v;
+  }
+  return v;
+}
+
+// List entries in flight per lane in the pair passes.
+constexpr int kBatch = 4;
+
+// The next kBatch list entries of atom i for this lane (entries past the list
+// end read as the atom itself with no image shift).
+template <int LPA>
+__device__ __forceinline__ void load_entries(const uint32_t* __restrict__ nbr, uint32_t N,
+                                             uint32_t i, int k0, int m, uint32_t self_e,
+                                             uint32_t (&e)[kBatch]) {
+  uint32_t off = ((uint32_t)k0 * N + i) * 4u;
+  const uint32_t step = (uint32_t)LPA * N * 4u;
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    e[u] = (k0 + u * LPA < m) ? ld32(nbr, off) : self_e;
+    off += step;
+  }
 }
 
 }  // namespace mdk

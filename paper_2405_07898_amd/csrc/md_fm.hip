@@ -389,7 +389,7 @@ md_params internal_params(double r_cut, int32_t cap) {
   p.lanes_per_atom = 1;
   p.sort_every = 0;
   p.list_mode = MD_LIST_FULL;
-  p.reserved = 0;
+  p.n_types = 0;
   return p;
 }
 

@@ -18,12 +18,14 @@ constexpr int kIndexBits = 26;       // list entry: j | image code << 26
 constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
 constexpr uint32_t kNoShift = 21u;   // code of the zero image shift: 1 | 1<<2 | 1<<4
 constexpr int kXcd = 8;              // MI355X dispatches workgroups round-robin over 8 XCDs
+constexpr int kMaxTypes = 4;         // atom types of the multi-species form
 
 // status word bits (device, sticky)
 constexpr int32_t ST_NBR_OVERFLOW = 1;
 constexpr int32_t ST_CELL_OVERFLOW = 2;
 constexpr int32_t ST_NONFINITE = 4;
 constexpr int32_t ST_LOST = 8;
+constexpr int32_t ST_BAD_TYPE = 16;
 constexpr int32_t ST_ERR_MASK = 0xff;
 constexpr int32_t ST_RHO_RANGE = 256;
 
@@ -35,6 +37,7 @@ enum StatusWord : int {
   SW_MAX_LIST = 3,
   SW_MAX_CELL = 4,
   SW_SCRATCH = 5,      // throw-away flag for timing launches
+  SW_TYPE_CHECK = 6,   // set when md_set_types finds a type out of range
   SW_STEPS = 8,        // int64
   SW_REBUILDS = 10,    // int64
   SW_LIST_TOTAL = 12,  // int64
@@ -102,7 +105,8 @@ struct Geometry {
   double rl2;       // (r_cut + skin)^2
   double lim2;      // (skin/2)^2
   double dt;
-  double acc;       // ftm2v / mass
+  double acc;       // ftm2v / mass (one species)
+  double acc_t[kMaxTypes];  // ftm2v / mass of each type (multi-species form)
   float rc2f;
   float pad;
 };
@@ -140,6 +144,31 @@ struct State {
   double4* qval;     // [cap][n] force on the i side of each pair slot (w unused)
   double* own_rho;   // [n] sum over the atom's own pair slots
   double4* own_f;    // [n] force sum over the atom's own pair slots
+  // multi-species form (null for one species)
+  uint8_t* type;       // type of each slot
+  uint8_t* type_orig;  // type of each atom, original order
+  uint8_t* sort_type;
+};
+
+// Tables of the multi-species form.  rho, phi share one knot grid (x0 = 0),
+// the embedding tables another.  The pair passes' rows are interleaved by
+// segment, so the rows one pair needs share a cache line (T = 2).
+struct MultiTables {
+  const double4* rho_seg;  // [nr-1][T] c0..c3 of rho_t(r), segment-major
+  const double* frow;      // [nr-1][seg_stride]: per segment the derivative quadratics
+                           // (3 doubles, in t, pre-scaled by 1/dx) of rho'_t for t < T,
+                           // then of phi'_ab for the pairs a <= b
+  const double4* phi_val;  // [T*T][nr-1] c0..c3 of phi_ab(r) (energy)
+  const double4* rho_val;  // [T][nr-1] c0..c3 of rho_t(r) (energy)
+  const double4* emb_val;  // [T][ne-1] c0..c3 of F_t(rho)
+  double r_inv_dx;
+  double e_x0, e_inv_dx;
+  int32_t nr, ne;
+  int32_t n_types;
+  int32_t seg_stride;      // doubles per segment of frow (a multiple of 16)
+  int32_t pair_row[kMaxTypes * kMaxTypes];  // row of phi'_ab within a segment of frow
+  int32_t lds_seg0;        // first segment of frow held in the force pass's LDS
+  int32_t lds_pad;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -185,11 +214,33 @@ hipError_t launch_half_force_integrate(const Launch& L, const Geometry& g, const
 hipError_t launch_half_force_only(const Launch& L, const Geometry& g, const State& s,
                                   const Tables& t, const double4* pos);
 hipError_t allow_half_lds(const Tables& t);
-hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double scale);
+// Multi-species pair passes, energy and type upload (md_multi.hip).
+size_t multi_density_lds_bytes(const MultiTables& t);  // 0 when the rows do not fit the LDS
+int multi_force_lds_seg0(int nr, int n_types);  // first force segment that fits the LDS
+size_t multi_force_lds_bytes(const MultiTables& t);
+hipError_t allow_multi_lds(const MultiTables& t);
+hipError_t launch_multi_density(const Launch& L, const Geometry& g, const State& s,
+                                const MultiTables& t, int lpa, const double4* pos,
+                                const int32_t* cond_zero, int32_t* clear_flag, int32_t* rclear,
+                                int64_t n_cells_total, bool want_rho);
+hipError_t launch_multi_force_integrate(const Launch& L, const Geometry& g, const State& s,
+                                        const MultiTables& t, int lpa, const double4* pos_in,
+                                        double4* pos_out, int32_t* flag_next, int32_t* rflag_next);
+hipError_t launch_multi_force_only(const Launch& L, const Geometry& g, const State& s,
+                                   const MultiTables& t, int lpa, const double4* pos);
+hipError_t launch_multi_energy(const Launch& L, const Geometry& g, const State& s,
+                               const MultiTables& t, double* out_pe_ke, int32_t n_rep);
+hipError_t launch_set_types(const Launch& L, const Geometry& g, const State& s,
+                            const int32_t* type_in, int32_t n_types, bool has_slots);
+hipError_t launch_energy_reduce(const Launch& L, const Geometry& g, const State& s,
+                                double* out_pe_ke, int32_t n_rep);
+// scale of the kick = coef * ftm2v / mass of the atom's type
+hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double coef);
 hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                          double* out_pe_ke, int32_t n_rep);
+// on-step velocity = v + coef * ftm2v / mass * f (coef = dt/2 after a step, else 0)
 hipError_t launch_export(const Launch& L, const Geometry& g, const State& s, double* x, double* v,
-                         double* f, double* rho, double* fp, double vhalf_to_onstep);
+                         double* f, double* rho, double* fp, double coef);
 hipError_t launch_export_cells(const Launch& L, const Geometry& g, const State& s, int32_t* cell);
 hipError_t launch_export_nbrs(const Launch& L, const Geometry& g, const State& s, int32_t* cnt,
                               int32_t* nbr, int32_t cap_out);

@@ -59,12 +59,13 @@ __global__ __launch_bounds__(64) void k_import(Geometry g, State s, const double
   s.pos[i] = p;
   s.vel[i] = make_double4(v[3 * i + 0], v[3 * i + 1], v[3 * i + 2], 0.0);
   s.id[i] = (int32_t)i;
+  if (s.type) s.type[i] = s.type_orig[i];
 }
 
 __global__ __launch_bounds__(64) void k_export(Geometry g, State s, double* __restrict__ x,
                                                double* __restrict__ v, double* __restrict__ f,
                                                double* __restrict__ rho, double* __restrict__ fp,
-                                               double vscale) {
+                                               double coef) {
   const AtomTile tl = g.atiles[blockIdx.x];
   if ((int)threadIdx.x >= tl.count) return;
   const RepDev& rp = g.reps[tl.rep];
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(64) void k_export(Geometry g, State s, double* __re
   const double4 fr = s.frc[i];
   if (v) {
     const double4 u = s.vel[i];
+    const double vscale = coef * acc_of(g, s, i);
     v[3 * o + 0] = fma(vscale, fr.x, u.x);
     v[3 * o + 1] = fma(vscale, fr.y, u.y);
     v[3 * o + 2] = fma(vscale, fr.z, u.z);
@@ -507,6 +509,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(State s, int64_t m, int32_
     s.sort_pos[base + r] = s.pos[e];
     s.sort_vel[base + r] = s.vel[e];
     s.sort_id[base + r] = key;
+    if (s.type) s.sort_type[base + r] = s.type[e];
   }
 }
 
@@ -516,6 +519,7 @@ __global__ __launch_bounds__(256) void k_sort_copyback(State s, int64_t n, int64
     s.pos[k] = s.sort_pos[k];
     s.vel[k] = s.sort_vel[k];
     s.id[k] = s.sort_id[k];
+    if (s.type) s.type[k] = s.sort_type[k];
   }
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
@@ -545,36 +549,14 @@ __device__ __forceinline__ void lane_sum2(float& s, float& c) {
   }
 }
 
-template <int LPA>
-__device__ __forceinline__ double lane_sum_sym(double v) {
-#pragma unroll
-  for (int o = 1; o < LPA; o <<= 1) {
-    const double w = __shfl_xor(v, o, 64);
-    v = ((threadIdx.x & o) == 0) ? v + w : w + v;
-  }
-  return v;
-}
 
 // Neighbours are processed in batches of kBatch per lane: the list entries of
 // a batch are loaded together, then all their positions, then all their table
 // rows, so each batch pays the position -> table latency chain once; the list
 // entries of the next batch are requested while a batch is in flight.
-constexpr int kBatch = 4;
 
 // rho_i of one atom (its lane's share), table rows from LDS.  Each batch
 // loads kBatch list entries, then their positions, then table rows.
-template <int LPA>
-__device__ __forceinline__ void load_entries(const uint32_t* __restrict__ nbr, uint32_t N,
-                                             uint32_t i, int k0, int m, uint32_t self_e,
-                                             uint32_t (&e)[kBatch]) {
-  uint32_t off = ((uint32_t)k0 * N + i) * 4u;
-  const uint32_t step = (uint32_t)LPA * N * 4u;
-#pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
-    e[u] = (k0 + u * LPA < m) ? ld32(nbr, off) : self_e;
-    off += step;
-  }
-}
 
 template <int PREC, int LPA>
 __device__ __forceinline__ double density_of(const Geometry& g, const State& s, const Tables& t,
@@ -886,10 +868,11 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry 
   }
 }
 
-__global__ __launch_bounds__(64) void k_halfkick(Geometry g, State s, double scale) {
+__global__ __launch_bounds__(64) void k_halfkick(Geometry g, State s, double coef) {
   const AtomTile tl = g.atiles[blockIdx.x];
   if ((int)threadIdx.x >= tl.count) return;
   const int64_t i = tl.begin + threadIdx.x;
+  const double scale = coef * acc_of(g, s, i);
   double4 v = s.vel[i];
   const double4 f = s.frc[i];
   v.x = fma(scale, f.x, v.x);
@@ -1186,8 +1169,14 @@ hipError_t allow_pair_lds(const Tables& t, int precision) {
   return allow_lds_one<1, 8>(d, f);
 }
 
-hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double scale) {
-  hipLaunchKernelGGL(k_halfkick, dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, scale);
+hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double coef) {
+  hipLaunchKernelGGL(k_halfkick, dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(const Launch& L, const Geometry& g, const State& s,
+                                double* out_pe_ke, int32_t n_rep) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(n_rep), dim3(256), 0, L.stream, g, s, out_pe_ke);
   return hipGetLastError();
 }
 
@@ -1204,9 +1193,9 @@ hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, con
 }
 
 hipError_t launch_export(const Launch& L, const Geometry& g, const State& s, double* x, double* v,
-                         double* f, double* rho, double* fp, double vscale) {
+                         double* f, double* rho, double* fp, double coef) {
   hipLaunchKernelGGL(k_export, dim3(L.atile_blocks), dim3(64), 0, L.stream, g, s, x, v, f, rho, fp,
-                     vscale);
+                     coef);
   return hipGetLastError();
 }
 

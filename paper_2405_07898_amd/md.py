@@ -41,7 +41,7 @@ class md_params(C.Structure):
                 ("precision", C.c_int32), ("nbr_capacity", C.c_int32),
                 ("cell_capacity", C.c_int32), ("chunk_steps", C.c_int32),
                 ("lanes_per_atom", C.c_int32), ("sort_every", C.c_int32),
-                ("list_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("list_mode", C.c_int32), ("n_types", C.c_int32)]
 
 
 class md_stats_t(C.Structure):
@@ -56,7 +56,7 @@ EXPORTED = [
     "md_workspace_size", "md_create", "md_set_state", "md_build_neighbors", "md_step",
     "md_energy", "md_get_state", "md_compute_forces", "md_stats", "md_get_cells",
     "md_get_neighbors", "md_launch_pass", "md_set_schedule", "md_autotune", "md_last_error",
-    "md_status_string", "md_destroy",
+    "md_status_string", "md_destroy", "md_create_multi", "md_set_types",
     "md_fm_workspace_size", "md_fm_create", "md_fm_forward", "md_fm_backward", "md_fm_destroy",
 ]
 
@@ -74,6 +74,9 @@ def lib():
             "md_workspace_size": (i32, [P(md_params), i32, P(i64), P(d), P(sz)]),
             "md_create": (i32, [P(vp), P(md_params), i32, P(i64), P(d), P(md_spline),
                                 P(md_spline), P(md_spline), vp, sz, vp]),
+            "md_create_multi": (i32, [P(vp), P(md_params), i32, P(i64), P(d), P(md_spline),
+                                      P(md_spline), P(md_spline), P(d), vp, sz, vp]),
+            "md_set_types": (i32, [vp, vp]),
             "md_set_state": (i32, [vp, vp, vp]),
             "md_build_neighbors": (i32, [vp]),
             "md_step": (i32, [vp, i64]),
@@ -144,9 +147,9 @@ class Spline:
 
 def make_params(*, mass, dt, r_cut, skin, ftm2v, kboltz=8.617333262e-5, precision=MD_FP64,
                 nbr_capacity=128, cell_capacity=64, chunk_steps=100, lanes_per_atom=0,
-                sort_every=1, list_mode=0) -> md_params:
+                sort_every=1, list_mode=0, n_types=0) -> md_params:
     return md_params(mass, dt, r_cut, skin, ftm2v, kboltz, precision, nbr_capacity, cell_capacity,
-                     chunk_steps, lanes_per_atom, sort_every, list_mode, 0)
+                     chunk_steps, lanes_per_atom, sort_every, list_mode, n_types)
 
 
 class System:
@@ -156,11 +159,13 @@ class System:
     with a cell grid of extent |L|.
 
     x, v: (N, 3) float64 (numpy or torch); boxes: (n_rep, 3); rep_atoms: (n_rep,).
+    tables: (phi, rho, F) for one species; with params.n_types = T > 1,
+    (phi[a][b], rho[t], F[t]) and `masses` (T,) for the multi-species form.
     Device memory (workspace, state staging) is allocated through torch.
     """
 
     def __init__(self, params: md_params, tables: Sequence, rep_atoms, boxes, *, stream=None,
-                 device="cuda"):
+                 device="cuda", masses=None):
         import torch
 
         self.torch = torch
@@ -170,7 +175,21 @@ class System:
         self.boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
         self.n_rep = int(self.rep_atoms.size)
         self.n = int(self.rep_atoms.sum())
-        self.splines = [Spline(t) for t in tables]
+        nt = int(params.n_types)
+        if nt > 1:
+            phi, rho, emb = tables
+            flat = [phi[a][b] for a in range(nt) for b in range(nt)]
+            self.multi = [(md_spline * len(ts))() for ts in (flat, rho, emb)]
+            self.splines = []
+            for arr, ts in zip(self.multi, (flat, rho, emb)):
+                for k, tab in enumerate(ts):
+                    sp = Spline(tab)
+                    self.splines.append(sp)
+                    arr[k] = sp.s
+            self.masses = np.ascontiguousarray(masses, dtype=np.float64)
+            assert self.masses.shape == (nt,)
+        else:
+            self.splines = [Spline(t) for t in tables]
         # a stream of its own (default priority): graphs cannot be captured on the
         # legacy default stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
@@ -182,12 +201,23 @@ class System:
                                    C.byref(nbytes)), "md_workspace_size")
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         ctx = C.c_void_p()
-        _check(L.md_create(C.byref(ctx), C.byref(params), self.n_rep,
-                           self.rep_atoms.ctypes.data_as(C.POINTER(C.c_int64)),
-                           self.boxes.ctypes.data_as(C.POINTER(C.c_double)),
-                           C.byref(self.splines[0].s), C.byref(self.splines[1].s),
-                           C.byref(self.splines[2].s), C.c_void_p(self.workspace.data_ptr()),
-                           nbytes.value, C.c_void_p(self.stream.cuda_stream)), "md_create")
+        if nt > 1:
+            sp = C.POINTER(md_spline)
+            _check(L.md_create_multi(C.byref(ctx), C.byref(params), self.n_rep,
+                                     self.rep_atoms.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     self.boxes.ctypes.data_as(C.POINTER(C.c_double)),
+                                     C.cast(self.multi[0], sp), C.cast(self.multi[1], sp),
+                                     C.cast(self.multi[2], sp),
+                                     self.masses.ctypes.data_as(C.POINTER(C.c_double)),
+                                     C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                     C.c_void_p(self.stream.cuda_stream)), "md_create_multi")
+        else:
+            _check(L.md_create(C.byref(ctx), C.byref(params), self.n_rep,
+                               self.rep_atoms.ctypes.data_as(C.POINTER(C.c_int64)),
+                               self.boxes.ctypes.data_as(C.POINTER(C.c_double)),
+                               C.byref(self.splines[0].s), C.byref(self.splines[1].s),
+                               C.byref(self.splines[2].s), C.c_void_p(self.workspace.data_ptr()),
+                               nbytes.value, C.c_void_p(self.stream.cuda_stream)), "md_create")
         self.ctx = ctx
 
     # -- lifecycle -----------------------------------------------------------
@@ -202,6 +232,15 @@ class System:
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         rc = lib().md_set_state(self.ctx, C.c_void_p(xd.data_ptr()), C.c_void_p(vd.data_ptr()))
         return _check(rc, "md_set_state", self.ctx)
+
+    def set_types(self, types):
+        """Atom types (original order, int32 in [0, n_types)); md_build_neighbors must follow."""
+        t = self.torch
+        td = t.as_tensor(np.ascontiguousarray(types, dtype=np.int32), device=self.device)
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        rc = lib().md_set_types(self.ctx, C.c_void_p(td.data_ptr()))
+        self.stream.synchronize()
+        return _check(rc, "md_set_types", self.ctx)
 
     def build_neighbors(self):
         return _check(lib().md_build_neighbors(self.ctx), "md_build_neighbors", self.ctx)

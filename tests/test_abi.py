@@ -108,3 +108,32 @@ def test_list_mode_validation_without_gpu(prec, mode, ok):
         extra = out.value - full.value
         per_atom = 52 + 52 * 128
         assert per_atom * 1000 <= extra <= per_atom * 1000 + 11 * 256
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+@pytest.mark.parametrize("nt,prec,mode,ok", [(0, 0, 0, True), (1, 0, 0, True), (2, 0, 0, True),
+                                             (4, 0, 0, True), (5, 0, 0, False), (-1, 0, 0, False),
+                                             (2, 1, 0, False), (2, 0, 1, False)])
+def test_type_count_validation_without_gpu(nt, prec, mode, ok):
+    """Several atom types: up to MD_MAX_TYPES, float64 and the full list only;
+    the workspace grows with the type count."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    n = (ctypes.c_int64 * 1)(1000)
+    b = np.array([20.0, 20.0, 20.0])
+
+    def size(**kw):
+        p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0, **kw)
+        out = ctypes.c_size_t(0)
+        rc = lib.md_workspace_size(ctypes.byref(p), 1, n,
+                                   b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(out))
+        return rc, out.value
+
+    rc, sz = size(n_types=nt, precision=prec, list_mode=mode)
+    assert (rc == 0) == ok, rc
+    if ok and nt > 1:
+        assert sz > size()[1]
