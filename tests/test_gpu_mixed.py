@@ -29,7 +29,8 @@ def _say(msg):
 
 def _pair_force_sums(x, box, fp):
     d = x[None, :, :] - x[:, None, :]
-    d -= box * np.round(d / box)
+    per = box > 0  # minimum image along periodic dimensions only
+    d[..., per] -= box[per] * np.round(d[..., per] / box[per])
     r = np.sqrt((d ** 2).sum(-1))
     np.fill_diagonal(r, np.inf)
     m = r < RC
@@ -38,16 +39,24 @@ def _pair_force_sums(x, box, fp):
     return s.sum(1) * 1.000001
 
 
-@pytest.mark.parametrize("ncell,temp,seed", [(6, 300.0, 61), (8, 2500.0, 62)])
-def test_mixed_forces_within_float32_bound(oracle_lib, ncell, temp, seed):
+MIXED_CASES = [
+    ("box_6cells_300K", lambda: configs.small_box(6, seed=61, temperature=300.0, sigma_x=0.02)),
+    ("box_8cells_2500K", lambda: configs.small_box(8, seed=62, temperature=2500.0,
+                                                   sigma_x=0.02 * np.sqrt(2500.0 / 300))),
+    ("slab_open_xy", lambda: configs.slab(7, 7, 5, seed=63, sigma_x=0.05, vacuum=6.0)),
+]
+
+
+@pytest.mark.parametrize("name,make", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_forces_within_float32_bound(oracle_lib, name, make):
     import torch
 
     from paper_2405_07898_amd import md
 
     assert torch.cuda.is_available()
     tabs = P.md_tables()
-    box = configs.small_box(ncell, seed=seed, temperature=temp, sigma_x=0.02 * np.sqrt(temp / 300))
-    _say(f"[gpu] mixed precision n={box.n} T={temp}")
+    box = make()
+    _say(f"[gpu] mixed precision case={name} n={box.n}")
     p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V,
                        precision=md.MD_MIXED)
     s = md.System(p, tabs, [box.n], box.box[None, :])

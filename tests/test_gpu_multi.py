@@ -60,8 +60,16 @@ def _disp(a, b, box):
     return d
 
 
+def _alloy_slab():
+    """A thin slab (open in x and y) whose sites are type 1 with probability 1/2."""
+    b = configs.slab(6, 7, 5, seed=77, sigma_x=0.05, vacuum=6.0)
+    b.types = (np.random.default_rng(78).random(b.n) < 0.5).astype(np.int32)
+    return b
+
+
 CASES = [
     ("alloy_6cells", lambda: configs.alloy_box(6, 71)),
+    ("alloy_slab_open_xy", _alloy_slab),
     ("alloy_hot_8cells", lambda: configs.alloy_box(8, 72, sigma_x=0.2, temperature=2000.0)),
     ("dilute_5cells", lambda: configs.alloy_box(5, 73, frac_1=0.1)),
 ]
