@@ -159,7 +159,10 @@ def cpu_baseline(box, tabs, budget_s: float = 15.0):
 
 
 def bench_small(torch, md, configs, tabs):
-    """2,000-atom box, 100-step graph chunks (launch-latency regime)."""
+    """2,000-atom box, 100-step chunks (launch-latency regime): a captured graph
+    per chunk, and for comparison one persistent cooperative launch per chunk."""
+    from workloads import potential
+
     box = configs.config_small()
     s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
     lpa, _ = s.autotune(50)
@@ -167,9 +170,20 @@ def bench_small(torch, md, configs, tabs):
     sec, _ = time_steps(torch, s, 2000)
     st = s.stats()
     s.close()
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+                       ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
+                       lanes_per_atom=8, nbr_capacity=128, cell_capacity=64,
+                       sort_every=SORT_EVERY, launch_mode=md.MD_LAUNCH_PERSISTENT)
+    sp = md.System(p, tabs, [box.n], box.box[None, :])
+    sp.set_state(box.x, box.v)
+    sp.build_neighbors()
+    sp.step(100)
+    sec_p, _ = time_steps(torch, sp, 2000)
+    sp.close()
     return {"n_atoms": box.n, "steps": 2000, "timesteps_per_s": round(2000 / sec, 1),
             "atom_steps_per_s": round(2000 / sec * box.n, 1), "lanes_per_atom": lpa,
-            "rebuilds": st["rebuilds"]}
+            "rebuilds": st["rebuilds"],
+            "persistent_launch_timesteps_per_s": round(2000 / sec_p, 1)}
 
 
 def bench_stable(torch, md, configs, potential, steps):

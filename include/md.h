@@ -56,6 +56,7 @@ typedef int32_t md_status;
 #define MD_E_ORDER (-8)         /* call out of order (e.g. md_step before md_build_neighbors) */
 #define MD_E_LOST_ATOM (-9)     /* an atom moved more than one box length past a periodic edge */
 #define MD_E_WORKSPACE (-10)    /* workspace too small or misaligned */
+#define MD_E_STALL (-11)        /* a grid barrier of a persistent launch timed out */
 #define MD_W_RHO_RANGE 1        /* some rho_i exceeded the F table; last cubic extrapolated */
 
 /* Precision of the pair passes. */
@@ -75,6 +76,18 @@ typedef int32_t md_status;
  *   bytes per atom of workspace. */
 #define MD_LIST_FULL 0
 #define MD_LIST_HALF 1
+
+/* How md_step launches a chunk of chunk_steps steps.
+ * MD_LAUNCH_GRAPH: a captured hipGraph of four kernels per step (binning and
+ *   list build run only when flagged).
+ * MD_LAUNCH_PERSISTENT: one cooperative launch runs the whole chunk, its
+ *   workgroups meeting at grid barriers between the phases of each step (for
+ *   small systems, where the graph's per-kernel launch cost dominates the
+ *   step; the paper's case for time steps per second at small N, Sec. II-B).
+ *   Full list and one atom type only; results are bitwise those of the graph.
+ *   A barrier that waits too long ends the launch with MD_E_STALL. */
+#define MD_LAUNCH_GRAPH 0
+#define MD_LAUNCH_PERSISTENT 1
 
 /* Most atom types of the multi-species form. */
 #define MD_MAX_TYPES 4
@@ -110,6 +123,8 @@ typedef struct md_params {
   int32_t list_mode;     /* MD_LIST_FULL or MD_LIST_HALF */
   int32_t n_types;       /* atom types: 0 or 1 (one species, md_create), or
                             2..MD_MAX_TYPES (md_create_multi) */
+  int32_t launch_mode;   /* MD_LAUNCH_GRAPH or MD_LAUNCH_PERSISTENT */
+  int32_t reserved;      /* 0 */
 } md_params;
 
 typedef struct md_ctx md_ctx;

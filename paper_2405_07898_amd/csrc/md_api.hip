@@ -59,6 +59,10 @@ md_status check_params(const md_params* p) {
   // several atom types: float64, full list
   if (p->n_types < 0 || p->n_types > kMaxTypes) return MD_E_ARG;
   if (p->n_types > 1 && (p->precision != MD_FP64 || p->list_mode != MD_LIST_FULL)) return MD_E_ARG;
+  if (p->launch_mode != MD_LAUNCH_GRAPH && p->launch_mode != MD_LAUNCH_PERSISTENT) return MD_E_ARG;
+  // the persistent step kernel runs the one-species full-list passes
+  if (p->launch_mode == MD_LAUNCH_PERSISTENT && (p->n_types > 1 || p->list_mode != MD_LIST_FULL))
+    return MD_E_ARG;
   return MD_OK;
 }
 
@@ -127,6 +131,7 @@ struct md_ctx {
   bool v_half = false;  // velocities are half-step (after build)
   int64_t chunks_since_sort = 0;
   hipGraphExec_t graph = nullptr;
+  int persist_cap = 0;  // most co-resident workgroups of the persistent kernel
   std::string err;
 };
 
@@ -320,6 +325,7 @@ md_status read_status(md_ctx* c, int32_t* words) {
 }
 
 md_status status_code(int32_t bits) {
+  if (bits & ST_STALL) return MD_E_STALL;
   if (bits & ST_NBR_OVERFLOW) return MD_E_NBR_OVERFLOW;
   if (bits & ST_CELL_OVERFLOW) return MD_E_CELL_OVERFLOW;
   if (bits & ST_LOST) return MD_E_LOST_ATOM;
@@ -388,6 +394,19 @@ md_status forces_now(md_ctx* c, bool want_rho) {
   HIPC(c, density_pass(c, s, c->lpa, s.pos, nullptr, nullptr, nullptr, want_rho));
   HIPC(c, force_only_pass(c, s, s.pos));
   return MD_OK;
+}
+
+// Workgroups of the persistent launch: enough that each takes about one tile
+// per pass (a tile = 64 atoms, 8 / lanes_per_atom tiles per workgroup
+// iteration), at least 8 and at most 64 (a barrier's cost grows with the
+// count) and never more than can be resident; a multiple of the XCD count.
+int persist_grid(const md_ctx* c) {
+  const int64_t tiles = (c->sz.n + 63) / 64 + c->n_rep;
+  const int per = std::max(1, (kPersistThreads / 64) / c->lpa);
+  int64_t g = (tiles + per - 1) / per;
+  g = std::min<int64_t>(std::max<int64_t>(g, kXcd), 64);
+  g = (g + kXcd - 1) / kXcd * kXcd;
+  return (int)std::min<int64_t>(g, std::max(c->persist_cap, kXcd));
 }
 
 // One step with eager launches (parity cur -> 1 - cur).
@@ -492,6 +511,7 @@ const char* md_status_string(md_status s) {
     case MD_E_HIP: return "HIP runtime error";
     case MD_E_ORDER: return "call out of order";
     case MD_E_LOST_ATOM: return "atom moved more than one box length";
+    case MD_E_STALL: return "a grid barrier of a persistent launch timed out";
     case MD_E_WORKSPACE: return "workspace too small or misaligned";
     case MD_W_RHO_RANGE: return "warning: density beyond the embedding table";
     default: return "unknown status";
@@ -738,6 +758,15 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
       return MD_E_TABLE;
     }
     e2 = allow_pair_lds(t, p->precision);
+    if (e2 == hipSuccess && p->launch_mode == MD_LAUNCH_PERSISTENT) {
+      if (persist_lds_bytes(t, p->precision, p->cell_capacity) > (size_t)lds_max) {
+        delete c;
+        return MD_E_ARG;
+      }
+      e2 = allow_persist_lds(t, p->precision, p->cell_capacity);
+      // one workgroup per CU fits the LDS the kernel takes
+      c->persist_cap = (c->L.persist_blocks / kXcd) * kXcd;
+    }
     if (e2 == hipSuccess && p->list_mode == MD_LIST_HALF) e2 = allow_half_lds(t);
     if (e2 != hipSuccess) {
       md_status r_ = hip_fail(c, e2, "hipFuncSetAttribute");
@@ -932,9 +961,16 @@ md_status md_step(md_ctx* c, int64_t n) {
         if ((s = rebuild_sorted(c, true)) != MD_OK) return s;
         c->chunks_since_sort = 0;
       }
-      if ((s = capture_chunk(c)) != MD_OK) return s;
-      HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, false));
-      HIPC(c, hipGraphLaunch(c->graph, c->L.stream));
+      if (c->p.launch_mode == MD_LAUNCH_PERSISTENT) {
+        HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, false));
+        HIPC(c, hipMemsetAsync(c->status + SW_BAR_COUNT, 0, 3 * sizeof(int32_t), c->L.stream));
+        HIPC(c, launch_persist(c->L, c->g, c->st[0], c->st[1], c->t, c->p.precision, c->lpa,
+                               chunk, c->sz.cells, persist_grid(c)));
+      } else {
+        if ((s = capture_chunk(c)) != MD_OK) return s;
+        HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, false));
+        HIPC(c, hipGraphLaunch(c->graph, c->L.stream));
+      }
       ++c->chunks_since_sort;
       done += chunk;
     } else {

@@ -390,6 +390,8 @@ md_params internal_params(double r_cut, int32_t cap) {
   p.sort_every = 0;
   p.list_mode = MD_LIST_FULL;
   p.n_types = 0;
+  p.launch_mode = MD_LAUNCH_GRAPH;
+  p.reserved = 0;
   return p;
 }
 

@@ -19,6 +19,7 @@ constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
 constexpr uint32_t kNoShift = 21u;   // code of the zero image shift: 1 | 1<<2 | 1<<4
 constexpr int kXcd = 8;              // MI355X dispatches workgroups round-robin over 8 XCDs
 constexpr int kMaxTypes = 4;         // atom types of the multi-species form
+constexpr int kPersistThreads = 512; // threads per workgroup of the persistent step kernel
 
 // status word bits (device, sticky)
 constexpr int32_t ST_NBR_OVERFLOW = 1;
@@ -26,6 +27,7 @@ constexpr int32_t ST_CELL_OVERFLOW = 2;
 constexpr int32_t ST_NONFINITE = 4;
 constexpr int32_t ST_LOST = 8;
 constexpr int32_t ST_BAD_TYPE = 16;
+constexpr int32_t ST_STALL = 32;      // a grid barrier of the persistent launch timed out
 constexpr int32_t ST_ERR_MASK = 0xff;
 constexpr int32_t ST_RHO_RANGE = 256;
 
@@ -42,6 +44,9 @@ enum StatusWord : int {
   SW_REBUILDS = 10,    // int64
   SW_LIST_TOTAL = 12,  // int64
   SW_SNAP_STEPS = 14,  // int64, SW_STEPS at the last snapshot
+  SW_BAR_COUNT = 20,   // grid barrier of the persistent launch: arrivals
+  SW_BAR_GEN = 21,     //   generation
+  SW_BAR_STOP = 22,    //   stop decision of the last arrival
   SW_WORDS = 64
 };
 
@@ -236,6 +241,13 @@ hipError_t launch_energy_reduce(const Launch& L, const Geometry& g, const State&
                                 double* out_pe_ke, int32_t n_rep);
 // scale of the kick = coef * ftm2v / mass of the atom's type
 hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, double coef);
+// nsteps (even) steps in one cooperative launch of `grid` workgroups; s0 / s1 =
+// the state with position buffer 0 / 1 current (buffer 0 current at entry).
+hipError_t launch_persist(const Launch& L, const Geometry& g, const State& s0, const State& s1,
+                          const Tables& t, int precision, int lpa, int32_t nsteps, int64_t ncells,
+                          int grid);
+hipError_t allow_persist_lds(const Tables& t, int precision, int cell_cap);
+size_t persist_lds_bytes(const Tables& t, int precision, int cell_cap);
 hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                          double* out_pe_ke, int32_t n_rep);
 // on-step velocity = v + coef * ftm2v / mass * f (coef = dt/2 after a step, else 0)

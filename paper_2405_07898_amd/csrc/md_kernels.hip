@@ -134,11 +134,11 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ p, int64
 // Launched with a grid smaller than the tile count (workgroup b takes tiles
 // b, b + G, ...), so that the launch that finds no rebuild due ends quickly.
 __device__ __forceinline__ void bin_tile(const Geometry& g, const State& s, const AtomTile& tl,
-                                         const int32_t* rcond) {
-  if ((int)threadIdx.x >= tl.count) return;
+                                         const int32_t* rcond, int a) {
+  if (a >= tl.count) return;
   if (rcond && rcond[tl.rep] == 0) return;  // this replica keeps its list
   const RepDev& rp = g.reps[tl.rep];
-  const int64_t i = tl.begin + threadIdx.x;
+  const int64_t i = tl.begin + a;
   bool bad = false;
   const double4 p = wrap_pos(s.pos[i], rp, bad);
   if (bad) {
@@ -190,7 +190,8 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
   const bool err = has_error(s.status);
   if (due == 0 || err) return;
   if (cond && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
-  for (int b = blockIdx.x; b < g.n_atiles; b += gridDim.x) bin_tile(g, s, g.atiles[b], rcond);
+  for (int b = blockIdx.x; b < g.n_atiles; b += gridDim.x)
+    bin_tile(g, s, g.atiles[b], rcond, (int)threadIdx.x);
 }
 
 // ============================================================ list build
@@ -251,10 +252,24 @@ __device__ __forceinline__ BuildLds carve_build_lds(char* p, int ccap) {
   return L;
 }
 
+// Synchronisation of the lanes that build one cell: the whole (one-wave)
+// workgroup, or only the wave when several waves of a workgroup build
+// different cells (LDS accesses of one wave are ordered by the fences).
+template <bool kWave>
+__device__ __forceinline__ void build_sync() {
+  if (kWave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <bool kWave>
 __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, const CellTile& ct,
-                                           const BuildLds& L) {
+                                           const BuildLds& L, int lane) {
   const RepDev& rp = g.reps[ct.rep];
-  const int lane = threadIdx.x;
   const int32_t nx = rp.nc[0], ny = rp.nc[1], nz = rp.nc[2];
   const int32_t c = ct.cell;
   const int32_t cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
@@ -289,11 +304,11 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
   }
   if (lane < 27) L.off[lane] = incl - n;
   if (lane == 26) L.off[27] = incl;
-  __syncthreads();
+  build_sync<kWave>();
   // centre atoms in increasing index, with their positions
   const int32_t qc = L.q[13], n_c = L.n[13];
   for (int u = lane; u < n_c; u += 64) L.raw[u] = s.bin_idx[(int64_t)qc * ccap + u];
-  __syncthreads();
+  build_sync<kWave>();
   for (int u = lane; u < n_c; u += 64) {
     const int32_t e = L.raw[u];
     int r = 0;
@@ -305,7 +320,7 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
     L.cy[r] = q.y;
     L.cz[r] = q.z;
   }
-  __syncthreads();
+  build_sync<kWave>();
   const double Lx = rp.box[0], Ly = rp.box[1], Lz = rp.box[2];
   const double rl2 = g.rl2;
   const int64_t N = g.n;
@@ -323,12 +338,12 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
       const int lo = L.off[lane] - base_off;
       for (int w = 0; w < n; ++w) L.cell[lo + w] = (int8_t)lane;
     }
-    __syncthreads();
+    build_sync<kWave>();
     for (int p = lane; p < T; p += 64) {
       const int sc = L.cell[p];
       L.raw[p] = s.bin_idx[(int64_t)L.q[sc] * ccap + (p + base_off - L.off[sc])];
     }
-    __syncthreads();
+    build_sync<kWave>();
     for (int p = lane; p < T; p += 64) {
       const int sc = L.cell[p];
       const int lo = L.off[sc] - base_off, nn = L.n[sc];
@@ -337,7 +352,7 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
       for (int w = lo; w < lo + nn; ++w) r += (L.raw[w] < e);
       L.idx[lo + r] = e;
     }
-    __syncthreads();
+    build_sync<kWave>();
     // candidates into registers (L.cell is per stencil cell, unchanged by the sort)
     double px[kBuildChunks], py[kBuildChunks], pz[kBuildChunks];
     double sx[kBuildChunks], sy[kBuildChunks], sz[kBuildChunks];
@@ -387,7 +402,7 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
       }
       if (lane == 0) L.base[u] = base;
     }
-    __syncthreads();
+    build_sync<kWave>();
     s0 = s1;
   }
   int32_t mx = 0;
@@ -429,7 +444,7 @@ __global__ __launch_bounds__(64, 6) void k_build(Geometry g, State s, const int3
     const CellTile ct = g.ctiles[b];
     if (ct.cell < 0) continue;
     if (rcond && rcond[ct.rep] == 0) continue;  // this replica keeps its list
-    build_cell(g, s, ct, lds);
+    build_cell<false>(g, s, ct, lds, (int)threadIdx.x);
     __syncthreads();  // the next cell reuses the staging arrays
   }
 }
@@ -625,6 +640,23 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
   return (double)sum + (double)comp;
 }
 
+// F'(rho_i) from the embedding table (float64 for both forms) into pos[i].w.
+template <int PREC>
+__device__ __forceinline__ void store_fprime(const State& s, const Tables& t, double4* pos,
+                                             int64_t i, double rho_i, int want_rho) {
+  const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
+  const int le = t.ne - 2;
+  const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
+  // past the last knot F continues along its end tangent: F' = F'(end)
+  const double te = fmin(xe - (double)ke, 1.0);
+  const double4 ce = t.emb_val[ke];
+  double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
+  if (PREC != 0) fp = (double)(float)fp;
+  pos[i].w = fp;
+  if (want_rho) s.rho[i] = rho_i;
+  if (xe > (double)(t.ne - 1)) set_bits(s.status, ST_RHO_RANGE);
+}
+
 // rho_i = sum_{j in list, r^2 < rc^2} rho(r_ij); F'_i stored in pos[i].w.
 // Side jobs used inside the step graph: clear the next step's rebuild flag,
 // and zero the bins after a rebuild (cond_zero set).
@@ -663,18 +695,7 @@ __global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
     const int64_t i = tl.begin + (active ? w.a : 0);
     const double rho_i = density_of<PREC, LPA>(g, s, t, rp, pos, lds_d4, i, active, w.sub);
     if (!active || w.sub != 0) continue;
-    // F'(rho_i) from the embedding table (float64 for both forms)
-    const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
-    const int le = t.ne - 2;
-    const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
-    // past the last knot F continues along its end tangent: F' = F'(end)
-    const double te = fmin(xe - (double)ke, 1.0);
-    const double4 ce = t.emb_val[ke];
-    double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
-    if (PREC != 0) fp = (double)(float)fp;
-    pos[i].w = fp;
-    if (want_rho) s.rho[i] = rho_i;
-    if (xe > (double)(t.ne - 1)) set_bits(s.status, ST_RHO_RANGE);
+    store_fprime<PREC>(s, t, pos, i, rho_i, want_rho);
   }
 }
 
@@ -781,6 +802,29 @@ __device__ __forceinline__ void fill_force_table(void* lds, const Tables& t) {
   }
 }
 
+// Leap-frog update of atom i from its force (Eq. leapfrog): v <- v + dt F
+// ftm2v/m, x' <- x + dt v into pos_out; returns whether it moved more than
+// skin/2 since the last list build (also true for NaN).
+__device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, int64_t i, double4 pi,
+                                         double4 v, double4 xr, double fx, double fy, double fz,
+                                         double4* __restrict__ pos_out) {
+  const double k = g.dt * g.acc;
+  v.x = fma(k, fx, v.x);
+  v.y = fma(k, fy, v.y);
+  v.z = fma(k, fz, v.z);
+  double4 xn;
+  xn.x = fma(g.dt, v.x, pi.x);
+  xn.y = fma(g.dt, v.y, pi.y);
+  xn.z = fma(g.dt, v.z, pi.z);
+  xn.w = 0.0;
+  pos_out[i] = xn;
+  s.vel[i] = v;
+  const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
+  const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
+  if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z)) set_bits(s.status, ST_NONFINITE);
+  return !(d2 <= g.lim2);
+}
+
 // Force pass fused with the leap-frog update (Eq. leapfrog):
 //   v <- v + dt F ftm2v/m ; x' <- x + dt v ; flag a rebuild if |x' - x_ref| > skin/2.
 // Positions ping-pong between two buffers (neighbours read pos_in while the
@@ -814,24 +858,7 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
     double fx, fy, fz;
     pair_forces<PREC, LPA>(g, s, t, rp, pos_in, lds_d4, i, active, w.sub, pi, fx, fy, fz);
     bool far = false;
-    if (active && w.sub == 0) {
-      const double k = g.dt * g.acc;
-      v.x = fma(k, fx, v.x);
-      v.y = fma(k, fy, v.y);
-      v.z = fma(k, fz, v.z);
-      double4 xn;
-      xn.x = fma(g.dt, v.x, pi.x);
-      xn.y = fma(g.dt, v.y, pi.y);
-      xn.z = fma(g.dt, v.z, pi.z);
-      xn.w = 0.0;
-      pos_out[i] = xn;
-      s.vel[i] = v;
-      const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
-      const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
-      far = !(d2 <= g.lim2);  // also true for NaN
-      if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z))
-        set_bits(s.status, ST_NONFINITE);
-    }
+    if (active && w.sub == 0) far = leapfrog(g, s, i, pi, v, xr, fx, fy, fz, pos_out);
     // one wave covers atoms of one tile, hence of one replica
     if (__ballot(far) != 0ull && lane_id() == 0) {
       *flag_next = 1;
@@ -865,6 +892,166 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry 
       s.frc[i] = make_double4(fx, fy, fz, 0.0);
       if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
     }
+  }
+}
+
+// ============================================================ persistent steps
+
+// Grid barrier of a cooperative launch (every workgroup is resident): one
+// arrival counter and a generation word.  The last workgroup to arrive reads
+// the status word and publishes whether to stop (an error was latched during
+// the phase), so all workgroups leave the step loop at the same barrier.  The
+// wait is bounded: past kBarrierSpins polls the workgroup raises ST_STALL and
+// stops, and so, in turn, do the others.  Release/acquire at agent scope make
+// the phase's global writes of every XCD visible after the barrier.
+constexpr long long kBarrierSpins = 4000000;
+
+// LDS of the force table (rows plus the fill's junk rows), 16-byte aligned.
+__host__ __device__ inline size_t persist_table_bytes(int nr, int prec) {
+  const size_t b = (size_t)(nr - 1) * (prec == 0 ? 3 * sizeof(double2)
+                                                 : sizeof(float4) + sizeof(float2)) +
+                   kLdsJunkBytes;
+  return (b + 15) & ~size_t(15);
+}
+
+__device__ bool grid_sync(int32_t* status) {
+  __shared__ int32_t s_go;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t* count = status + SW_BAR_COUNT;
+    int32_t* gen = status + SW_BAR_GEN;
+    int32_t* stop = status + SW_BAR_STOP;
+    const int32_t g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t arrived =
+        __hip_atomic_fetch_add(count, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t go = 1;
+    if (arrived == (int32_t)gridDim.x - 1) {
+      const int32_t bits = __hip_atomic_load(status + SW_BITS, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      go = (bits & ST_ERR_MASK) ? 0 : 1;
+      __hip_atomic_store(count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(stop, go ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gen, g0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        if (++spins > kBarrierSpins) {
+          set_bits(status, ST_STALL);
+          go = -1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (go > 0) go = __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 0 : 1;
+    }
+    s_go = go > 0;
+  }
+  __syncthreads();
+  return s_go != 0;
+}
+
+// nsteps whole steps in one cooperative launch (small systems, where graph
+// node launches dominate): per step, when the previous step flagged it,
+// binning, barrier, list build, barrier; then density, barrier, force pass
+// fused with the leap-frog update, barrier.  The phases are the device code of
+// the per-phase kernels (same arithmetic, same order: results are bitwise
+// those of the graph path).  The force table stays in the LDS for the whole
+// launch; the density rows are read from global memory; each wave builds its
+// own cells with its own staging area.  s0 / s1: the state with buffer 0 / 1
+// current; nsteps is even, so buffer 0 is current again at the end.
+template <int PREC, int LPA>
+__global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s0, State s1,
+                                                             Tables t, int32_t nsteps,
+                                                             int64_t ncells) {
+  extern __shared__ double4 lds_d4[];
+  fill_force_table<PREC>(lds_d4, t);
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int nwaves = (int)blockDim.x >> 6;
+  const size_t bl = (build_lds_bytes(g.cell_cap) + 15) & ~size_t(15);
+  char* build_base = reinterpret_cast<char*>(lds_d4) + persist_table_bytes(t.nr, PREC);
+  const BuildLds L = carve_build_lds(build_base + (size_t)wave * bl, g.cell_cap);
+  const void* dens_tab = PREC == 0 ? static_cast<const void*>(t.rho_val)
+                                   : static_cast<const void*>(t.rho_val32);
+  int32_t* status = s0.status;
+  // the first barrier also publishes one decision on errors latched before the launch
+  if (!grid_sync(status)) return;
+  const int64_t gstride = (int64_t)gridDim.x * nwaves;
+  const int64_t gwave = (int64_t)blockIdx.x * nwaves + wave;
+  for (int32_t step = 0; step < nsteps; ++step) {
+    const int k = step & 1;
+    const State& s = k ? s1 : s0;
+    int32_t* fl_cur = status + (k == 0 ? SW_FLAG0 : SW_FLAG1);
+    int32_t* fl_nxt = status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
+    const int32_t* rf_cur = s.rflag + (k == 0 ? 0 : g.n_rep);
+    int32_t* rf_nxt = s.rflag + (k == 0 ? g.n_rep : 0);
+    const bool rebuild =
+        __hip_atomic_load(fl_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (rebuild) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(status, SW_REBUILDS) += 1ull;
+      for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rf_cur, lane);
+      if (!grid_sync(status)) return;
+      for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
+        const CellTile ct = g.ctiles[b];
+        if (ct.cell < 0 || rf_cur[ct.rep] == 0) continue;
+        build_cell<true>(g, s, ct, L, lane);
+        build_sync<true>();  // the wave's next cell reuses its staging arrays
+      }
+      if (!grid_sync(status)) return;
+    }
+    // density pass; side jobs: zero the bins after a rebuild, clear the next
+    // step's rebuild flags
+    if (rebuild) {
+      for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncells;
+           c += (int64_t)gridDim.x * blockDim.x)
+        s.bin_cnt[c] = 0;
+    }
+    if (blockIdx.x == 0) {
+      if (threadIdx.x == 0) *fl_nxt = 0;
+      for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rf_nxt[r] = 0;
+    }
+    {
+      const TileWalk w = tile_walk<LPA>();
+      for (int64_t it = w.q;; it += w.tpi) {
+        const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
+        if (b >= g.n_atiles) break;
+        const AtomTile tl = g.atiles[b];
+        const bool active = w.a < tl.count;
+        const RepDev& rp = g.reps[tl.rep];
+        const int64_t i = tl.begin + (active ? w.a : 0);
+        const double rho_i = density_of<PREC, LPA>(g, s, t, rp, s.pos, dens_tab, i, active, w.sub);
+        if (!active || w.sub != 0) continue;
+        store_fprime<PREC>(s, t, s.pos, i, rho_i, 0);
+      }
+    }
+    if (!grid_sync(status)) return;
+    // force pass fused with the leap-frog update, into the other buffer
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(status, SW_STEPS) += 1ull;
+    {
+      const TileWalk w = tile_walk<LPA>();
+      for (int64_t it = w.q;; it += w.tpi) {
+        const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
+        if (b >= g.n_atiles) break;
+        const AtomTile tl = g.atiles[b];
+        const bool active = w.a < tl.count;
+        const RepDev& rp = g.reps[tl.rep];
+        const int64_t i = tl.begin + (active ? w.a : 0);
+        const double4 pi = s.pos[i];
+        double4 v = make_double4(0.0, 0.0, 0.0, 0.0), xr = v;
+        if (active && w.sub == 0) {
+          v = s.vel[i];
+          xr = s.xref[i];
+        }
+        double fx, fy, fz;
+        pair_forces<PREC, LPA>(g, s, t, rp, s.pos, lds_d4, i, active, w.sub, pi, fx, fy, fz);
+        bool far = false;
+        if (active && w.sub == 0) far = leapfrog(g, s, i, pi, v, xr, fx, fy, fz, s.pos_alt);
+        if (__ballot(far) != 0ull && lane_id() == 0) {
+          *fl_nxt = 1;
+          rf_nxt[tl.rep] = 1;
+        }
+      }
+    }
+    if (!grid_sync(status)) return;
   }
 }
 
@@ -1139,6 +1326,57 @@ hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s,
   if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_O) }
   MDK_LPA_SWITCH(1, lpa, MDK_O)
 #undef MDK_O
+}
+
+// The persistent step kernel: the force table (as in the force pass) and one
+// build staging area per wave.
+size_t persist_lds_bytes(const Tables& t, int prec, int cell_cap) {
+  const size_t bl = (build_lds_bytes(cell_cap) + 15) & ~size_t(15);
+  return persist_table_bytes(t.nr, prec) + (size_t)(kPersistThreads / 64) * bl;
+}
+
+template <int PREC, int LPA>
+static hipError_t persist_go(const Launch& L, const Geometry& g, const State& s0, const State& s1,
+                             const Tables& t, int32_t nsteps, int64_t ncells, int grid) {
+  Geometry ga = g;
+  State a0 = s0, a1 = s1;
+  Tables ta = t;
+  int32_t n = nsteps;
+  int64_t m = ncells;
+  void* args[] = {&ga, &a0, &a1, &ta, &n, &m};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<PREC, LPA>),
+                                    dim3(grid), dim3(kPersistThreads), args,
+                                    (unsigned int)persist_lds_bytes(t, PREC, g.cell_cap), L.stream);
+}
+
+hipError_t launch_persist(const Launch& L, const Geometry& g, const State& s0, const State& s1,
+                          const Tables& t, int precision, int lpa, int32_t nsteps, int64_t ncells,
+                          int grid) {
+#define MDK_P(P, Lp) persist_go<P, Lp>(L, g, s0, s1, t, nsteps, ncells, grid)
+  if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_P) }
+  MDK_LPA_SWITCH(1, lpa, MDK_P)
+#undef MDK_P
+}
+
+template <int PREC, int LPA>
+static hipError_t allow_persist_one(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist<PREC, LPA>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t allow_persist_lds(const Tables& t, int precision, int cell_cap) {
+  const size_t b = persist_lds_bytes(t, precision, cell_cap);
+  hipError_t e;
+  if (precision == 0) {
+    if ((e = allow_persist_one<0, 1>(b)) != hipSuccess) return e;
+    if ((e = allow_persist_one<0, 2>(b)) != hipSuccess) return e;
+    if ((e = allow_persist_one<0, 4>(b)) != hipSuccess) return e;
+    return allow_persist_one<0, 8>(b);
+  }
+  if ((e = allow_persist_one<1, 1>(b)) != hipSuccess) return e;
+  if ((e = allow_persist_one<1, 2>(b)) != hipSuccess) return e;
+  if ((e = allow_persist_one<1, 4>(b)) != hipSuccess) return e;
+  return allow_persist_one<1, 8>(b);
 }
 
 // Dynamic LDS above the default limit must be allowed per kernel.

@@ -18,9 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libmdeam.so")
 MD_OK = 0
 MD_E_ARG, MD_E_BOX, MD_E_TABLE, MD_E_NBR_OVERFLOW, MD_E_CELL_OVERFLOW = -1, -2, -3, -4, -5
 MD_E_NONFINITE, MD_E_HIP, MD_E_ORDER, MD_E_LOST_ATOM, MD_E_WORKSPACE = -6, -7, -8, -9, -10
+MD_E_STALL = -11
 MD_W_RHO_RANGE = 1
 MD_FP64, MD_MIXED = 0, 1
 MD_LIST_FULL, MD_LIST_HALF = 0, 1
+MD_LAUNCH_GRAPH, MD_LAUNCH_PERSISTENT = 0, 1
 PASS_DENSITY, PASS_FORCE, PASS_BUILD, PASS_BIN, PASS_FORCE_RAW = 0, 1, 2, 3, 4
 
 
@@ -41,7 +43,8 @@ class md_params(C.Structure):
                 ("precision", C.c_int32), ("nbr_capacity", C.c_int32),
                 ("cell_capacity", C.c_int32), ("chunk_steps", C.c_int32),
                 ("lanes_per_atom", C.c_int32), ("sort_every", C.c_int32),
-                ("list_mode", C.c_int32), ("n_types", C.c_int32)]
+                ("list_mode", C.c_int32), ("n_types", C.c_int32),
+                ("launch_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class md_stats_t(C.Structure):
@@ -147,9 +150,9 @@ class Spline:
 
 def make_params(*, mass, dt, r_cut, skin, ftm2v, kboltz=8.617333262e-5, precision=MD_FP64,
                 nbr_capacity=128, cell_capacity=64, chunk_steps=100, lanes_per_atom=0,
-                sort_every=1, list_mode=0, n_types=0) -> md_params:
+                sort_every=1, list_mode=0, n_types=0, launch_mode=0) -> md_params:
     return md_params(mass, dt, r_cut, skin, ftm2v, kboltz, precision, nbr_capacity, cell_capacity,
-                     chunk_steps, lanes_per_atom, sort_every, list_mode, n_types)
+                     chunk_steps, lanes_per_atom, sort_every, list_mode, n_types, launch_mode, 0)
 
 
 class System:

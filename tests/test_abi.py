@@ -137,3 +137,23 @@ def test_type_count_validation_without_gpu(nt, prec, mode, ok):
     assert (rc == 0) == ok, rc
     if ok and nt > 1:
         assert sz > size()[1]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+@pytest.mark.parametrize("launch,mode,nt,ok", [(0, 0, 0, True), (1, 0, 0, True), (2, 0, 0, False),
+                                               (1, 1, 0, False), (1, 0, 2, False)])
+def test_launch_mode_validation_without_gpu(launch, mode, nt, ok):
+    """The persistent launch runs the one-species full-list passes only."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0, launch_mode=launch,
+                       list_mode=mode, n_types=nt)
+    n = (ctypes.c_int64 * 1)(1000)
+    b = np.array([20.0, 20.0, 20.0])
+    out = ctypes.c_size_t(0)
+    rc = lib.md_workspace_size(ctypes.byref(p), 1, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(out))
+    assert (rc == 0) == ok
