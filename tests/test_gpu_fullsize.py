@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import bench
+from mixed_bound import pair_bounds
 from workloads import configs, potential as P
 
 pytestmark = pytest.mark.gpu
@@ -99,3 +100,50 @@ def test_full_size_trajectory_100_steps(md, tabs, oracle_lib, name, make):
     assert np.max(np.abs(d)) < 1e-9
     assert np.max(np.abs(v.cpu().numpy() - out["v"])) < 1e-11
     assert st["steps"] == 100
+
+
+def test_full_size_mixed_810k_within_float32_bound(md, tabs, oracle_lib):
+    """The mixed form at 802,344 atoms, launched as the benchmark launches it:
+    every rho_i and force within the float32 bound (mixed_bound.py) of the
+    float64 oracle."""
+    box = configs.config_810k()
+    _say(f"[gpu] full size mixed: n={box.n}")
+    s = bench.make_system(md, box, tabs, precision=md.MD_MIXED, chunk=100)
+    s.autotune(5)
+    f, rho, _ = (t.cpu().numpy() for t in s.compute_forces())
+    s.close()
+    ref = oracle_lib.forces_at(box.x, box.box, tabs, RC, SKIN)
+    cnt, nbr, _ = oracle_lib.neighbor_list(box.x, box.box, RC + SKIN, cap=128)
+    rho_bound, f_bound = pair_bounds(box.x, box.box, ref["fp"], cnt, nbr)
+    assert np.all(np.abs(rho - ref["rho"]) <= rho_bound)
+    err = np.linalg.norm(f - ref["f"], axis=1)
+    assert np.all(err <= f_bound), float(np.max(err / f_bound))
+    assert np.max(err) > 1e-12  # float32 arithmetic, not the float64 path
+
+
+def test_full_batch_256_replicas_sampled(md, tabs, oracle_lib):
+    """All 256 replicas (1.5 M atoms) in one context, launched as the benchmark
+    launches them (100-step graph chunk, autotuned lanes per atom); 8 replicas,
+    drawn with a fixed seed, follow the oracle's own runs."""
+    reps = configs.config_batch(256)
+    _say(f"[gpu] full batch: {len(reps)} replicas, n={sum(b.n for b in reps)}")
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V,
+                       chunk_steps=100, nbr_capacity=128, cell_capacity=64)
+    s = md.System(p, tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
+    s.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
+    s.build_neighbors()
+    s.autotune(5)
+    s.step(100)
+    x, v, _ = (t.cpu().numpy() for t in s.get_state())
+    assert s.stats()["steps"] == 100
+    s.close()
+    off = np.concatenate([[0], np.cumsum([b.n for b in reps])])
+    for r in np.sort(np.random.default_rng(11).choice(len(reps), 8, replace=False)):
+        b = reps[r]
+        out = oracle_lib.md_run(b.x, b.v, b.box, tabs, 100, mass=configs.MASS, dt=configs.DT,
+                                r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+        assert out["code"] == 0
+        d = x[off[r]:off[r + 1]] - out["x"]
+        d -= b.box * np.round(d / b.box)
+        assert np.max(np.abs(d)) < 1e-9, r
+        assert np.max(np.abs(v[off[r]:off[r + 1]] - out["v"])) < 1e-11, r

@@ -1,20 +1,14 @@
 """Mixed-precision form (float32 pair terms, compensated float32 sums, float64
-state) against the float64 oracle on identical positions.
-
-Bound: each pair term carries a relative error of at most about 16 u
-(u = 2^-24: rounding of the separation, r^2, the hardware rsqrt, the
-spline segment and the products), and the TwoSum accumulation adds
-O(n u^2).  The pair force f_ij = (F'_i + F'_j) rho'(r) + phi'(r) is a sum of
-an embedding and a pair term that cancel in part (exactly so in the
-lattice-sum sense at zero pressure), and each carries its error relative to
-its own size, so |dF_i| <= 16 u sum_j (|(F'_i + F'_j) rho'(r_ij)| + |phi'(r_ij)|)
-and |d rho_i| <= 16 u rho_i.  The sums are computed here by numpy from the
-analytic potential (a bound on the tabulated one within 1e-6)."""
+state) against the float64 oracle on identical positions, within the error
+bound derived term by term in mixed_bound.py (float32 separation, r^2, rsqrt,
+segment and Horner cubic; their effect on each term is its size plus r times
+its slope)."""
 import sys
 
 import numpy as np
 import pytest
 
+from mixed_bound import pair_bounds
 from workloads import configs, potential as P
 
 pytestmark = pytest.mark.gpu
@@ -25,18 +19,6 @@ U = 2.0 ** -24
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
-
-
-def _pair_force_sums(x, box, fp):
-    d = x[None, :, :] - x[:, None, :]
-    per = box > 0  # minimum image along periodic dimensions only
-    d[..., per] -= box[per] * np.round(d[..., per] / box[per])
-    r = np.sqrt((d ** 2).sum(-1))
-    np.fill_diagonal(r, np.inf)
-    m = r < RC
-    rr = np.where(m, r, 1.0)
-    s = np.where(m, np.abs((fp[:, None] + fp[None, :]) * P.drho(rr)) + np.abs(P.dphi(rr)), 0.0)
-    return s.sum(1) * 1.000001
 
 
 MIXED_CASES = [
@@ -65,9 +47,10 @@ def test_mixed_forces_within_float32_bound(oracle_lib, name, make):
     f, rho, fp = (t.cpu().numpy() for t in s.compute_forces())
     s.close()
     ref = oracle_lib.forces_at(box.x, box.box, tabs, RC, SKIN)
-    assert np.all(np.abs(rho - ref["rho"]) <= 16 * U * ref["rho"] + 1e-12)
-    bound = 16 * U * _pair_force_sums(box.x, box.box, ref["fp"])
+    cnt, nbr, _ = oracle_lib.neighbor_list(box.x, box.box, RC + SKIN, cap=128)
+    rho_bound, f_bound = pair_bounds(box.x, box.box, ref["fp"], cnt, nbr)
+    assert np.all(np.abs(rho - ref["rho"]) <= rho_bound), np.max(np.abs(rho - ref["rho"]) / rho_bound)
     err = np.linalg.norm(f - ref["f"], axis=1)
-    assert np.all(err <= bound), np.max(err / bound)
+    assert np.all(err <= f_bound), np.max(err / f_bound)
     # and it is not accidentally the float64 path: errors are of float32 size
     assert np.max(err) > 1e-12
