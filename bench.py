@@ -424,10 +424,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--secondary-steps", type=int, default=1000)
+    ap.add_argument("--secondary-steps", type=int, default=5000)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--lpa", type=int, default=0)
-    ap.add_argument("--batched-steps", type=int, default=300)
+    ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--sequential-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM counters)")

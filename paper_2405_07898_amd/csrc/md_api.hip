@@ -631,7 +631,6 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
     memset(&d, 0, sizeof(d));
     for (int k = 0; k < 3; ++k) {
       d.box[k] = reps[r].box[k];
-      d.half[k] = 0.5 * reps[r].box[k];
       d.nc[k] = reps[r].nc[k];
       d.inv_cell[k] = (double)reps[r].nc[k] / reps[r].box[k];
     }
@@ -1130,6 +1129,7 @@ md_status md_launch_pass(md_ctx* c, int32_t pass, int32_t reps) {
       }
       HIPC(c, launch_build(c->L, c->g, s, nullptr, nullptr));
       HIPC(c, launch_zero_bins(c->L, s, c->sz.cells));
+      HIPC(c, half_reindex(c, s));
       break;
   }
   return MD_OK;

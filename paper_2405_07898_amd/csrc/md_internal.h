@@ -53,8 +53,7 @@ enum StatusWord : int {
 // ---------------------------------------------------------------- structs
 
 struct RepDev {
-  double box[3];
-  double half[3];
+  double box[3];      // lengths (periodic) or cell-grid extents (open)
   double inv_cell[3];
   int64_t atom0;
   int32_t n_atoms;

@@ -543,12 +543,6 @@ __global__ __launch_bounds__(256) void k_sort_copyback(State s, int64_t n, int64
 
 // ============================================================ density pass
 
-template <int LPA>
-__device__ __forceinline__ double lane_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < LPA; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <int LPA>
 __device__ __forceinline__ void lane_sum2(float& s, float& c) {
