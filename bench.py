@@ -152,10 +152,32 @@ def cpu_baseline(box, tabs, budget_s: float = 15.0):
     out = oracle.md_run(box.x, box.v, box.box, tabs, steps, **kw)
     dt = time.perf_counter() - t0
     assert out["code"] == 0
+    # the same oracle on one thread (bitwise the same results), a shorter sample
+    oracle.set_threads(1)
+    try:
+        s1 = max(3, steps // (4 * max(threads, 1)))
+        t0 = time.perf_counter()
+        out1 = oracle.md_run(box.x, box.v, box.box, tabs, s1, **kw)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    assert out1["code"] == 0
     return dict(value=steps / dt, unit="timesteps/s", cores=threads, kind="oracle",
                 sample=f"{steps} velocity-Verlet steps of the same {box.n}-atom float64 workload "
                        f"(first list build included), OpenMP over atoms",
-                atom_steps_per_s=steps * box.n / dt)
+                atom_steps_per_s=steps * box.n / dt, cpu_model=_cpu_model(),
+                single_thread={"value": s1 / dt1, "unit": "timesteps/s", "steps": s1})
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_small(torch, md, configs, tabs):
