@@ -202,3 +202,13 @@ def test_error_paths(md, tabs):
         s.build_neighbors()
     assert e.value.code == md.MD_E_CELL_OVERFLOW
     s.close()
+    # two coincident atoms: r = 0 gives a non-finite force (every table index
+    # stays clamped to its table)
+    x = box.x.copy()
+    x[5] = x[4]
+    s = md.System(_params(md), tabs, [box.n], box.box[None, :])
+    s.set_state(x, box.v)
+    with pytest.raises(md.MDError) as e:
+        s.build_neighbors()
+    assert e.value.code == md.MD_E_NONFINITE
+    s.close()

@@ -164,3 +164,33 @@ def test_periodic_edge_still_rejected(md, tabs):
     with pytest.raises(Exception):
         md.System(md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN,
                                  ftm2v=configs.FTM2V), tabs, [box.n], bad[None, :])
+
+
+def test_open_cluster_trajectory_and_momenta(md, tabs, oracle_lib):
+    """A rotating cluster in a box open in every dimension: the oracle's
+    trajectory, and linear and angular momentum kept to rounding."""
+    x = configs.bcc_block(3, 3, 3) + 10.0
+    rng = np.random.default_rng(91)
+    x = x + 0.02 * rng.standard_normal(x.shape)
+    v = configs.maxwell_boltzmann(rng, x.shape[0], 100.0)
+    c = x.mean(axis=0)
+    v = v + np.cross(np.array([0.3, -0.5, 1.0]) * 0.002, x - c)
+    box = configs.Box(x=x, v=v, box=-np.full(3, 40.0), n_cells=3, temperature=100.0,
+                      site_ids=np.arange(x.shape[0], dtype=np.int64))
+    _say(f"[gpu] open cluster n={box.n}")
+    s = _system(md, tabs, box, chunk_steps=100)
+    s.build_neighbors()
+    s.step(400)
+    xg, vg, _ = (t.cpu().numpy() for t in s.get_state())
+    s.close()
+    out = oracle_lib.md_run(x, v, box.box, tabs, 400, mass=configs.MASS, dt=configs.DT, r_cut=RC,
+                            skin=SKIN, ftm2v=configs.FTM2V)
+    assert np.max(np.abs(xg - out["x"])) < 1e-9
+    assert np.max(np.abs(vg - out["v"])) < 1e-11
+
+    def ang(xx, vv):
+        return configs.MASS * np.cross(xx - xx.mean(axis=0), vv).sum(axis=0)
+
+    l0 = ang(x, v)
+    assert np.max(np.abs(ang(xg, vg) - l0)) < 1e-9 * np.linalg.norm(l0)
+    assert np.max(np.abs(vg.sum(axis=0) - v.sum(axis=0))) < 1e-12 * np.abs(v).sum()

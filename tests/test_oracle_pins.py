@@ -400,3 +400,46 @@ def test_dimer_in_open_box(oracle_lib, md_tables, r):
     assert abs(res["pe"] - e) < 1e-6
     np.testing.assert_allclose(res["f"][0], [s, 0, 0], atol=1e-6)
     np.testing.assert_allclose(res["f"][1], [-s, 0, 0], atol=1e-6)
+
+
+def _cluster(n_cells=3, seed=91, temperature=100.0, omega=0.002):
+    """A small BCC cluster in a box open in every dimension, with thermal
+    velocities plus a rigid rotation about its centre (rad/fs)."""
+    x = configs.bcc_block(n_cells, n_cells, n_cells) + 10.0
+    rng = np.random.default_rng(seed)
+    x = x + 0.02 * rng.standard_normal(x.shape)
+    v = configs.maxwell_boltzmann(rng, x.shape[0], temperature)
+    c = x.mean(axis=0)
+    v = v + np.cross(np.array([0.3, -0.5, 1.0]) * omega, x - c)
+    return x, v, -np.full(3, 40.0)
+
+
+def _angular_momentum(x, v):
+    c = x.mean(axis=0)
+    return configs.MASS * np.cross(x - c, v).sum(axis=0)
+
+
+def test_open_cluster_conserves_momenta(oracle_lib, md_tables):
+    """No images in any dimension: the forces are central and pairwise opposite,
+    so velocity Verlet keeps the linear and the angular momentum to rounding."""
+    x, v, box = _cluster()
+    p0, l0 = configs.MASS * v.sum(axis=0), _angular_momentum(x, v)
+    out = oracle_lib.md_run(x, v, box, md_tables, 400, mass=configs.MASS, dt=configs.DT, r_cut=RC,
+                            skin=SKIN, ftm2v=configs.FTM2V)
+    assert out["code"] == 0
+    p1 = configs.MASS * out["v"].sum(axis=0)
+    # the centre of mass moves with the (conserved) momentum; the angular
+    # momentum is taken about it
+    l1 = _angular_momentum(out["x"], out["v"])
+    assert np.max(np.abs(p1 - p0)) < 1e-12 * configs.MASS * np.abs(v).sum()
+    assert np.max(np.abs(l1 - l0)) < 1e-9 * np.linalg.norm(l0)
+    assert np.linalg.norm(l0) > 1.0  # the rotation is not negligible
+
+
+def test_coincident_atoms_are_reported_nonfinite(oracle_lib, md_tables):
+    b = configs.small_box(6, seed=92)
+    x = b.x.copy()
+    x[5] = x[4]
+    out = oracle_lib.md_run(x, b.v, b.box, md_tables, 2, mass=configs.MASS, dt=configs.DT, r_cut=RC,
+                            skin=SKIN, ftm2v=configs.FTM2V)
+    assert out["code"] == oracle_lib.OR_E_NONFINITE
