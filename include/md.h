@@ -268,7 +268,9 @@ void md_destroy(md_ctx* ctx);
 typedef struct md_fm_ctx md_fm_ctx;
 
 /* Bytes of device workspace for n_cfg configs (host rep_atoms, rep_box) with
- * n_knots-knot tables for each of phi, rho, F. */
+ * n_knots-knot tables for each of phi, rho, F.  Returns MD_E_TABLE when the
+ * three tables have more than 2048 segments together (the coefficient
+ * gradients are accumulated in one 64 KB LDS histogram per workgroup). */
 md_status md_fm_workspace_size(int32_t n_cfg, const int64_t* cfg_atoms, const double* cfg_box,
                                double r_cut, int32_t nbr_capacity, const int32_t n_knots[3],
                                size_t* bytes);

@@ -35,6 +35,8 @@ using namespace mdk;
 namespace {
 
 constexpr int kFmBlocks = 512;  // persistent blocks of the coefficient pass
+constexpr int kFmSplit = 16;    // first-stage groups of block histograms in the reduction
+constexpr size_t kFmLds = 65536;  // LDS of the coefficient pass's histogram
 
 struct FmSpline {
   const double* coef;  // device [(n-1)][4]
@@ -59,6 +61,7 @@ struct FmArgs {
   double* partial;   // [tiles]
   double* loss;      // [1]
   unsigned long long* hist;  // [kFmBlocks][nbins]
+  unsigned long long* part;  // [kFmSplit][nbins] first-stage sums of hist
   double* bound;     // [tiles] largest gradient term per tile
   double* scale;     // [2]: fixed-point scale and its inverse
   int32_t* flag;     // overflow / non-finite
@@ -329,13 +332,34 @@ __global__ __launch_bounds__(64) void k_fm_coef(FmArgs a) {
   for (int b = threadIdx.x; b < nb; b += blockDim.x) a.hist[(int64_t)blockIdx.x * nb + b] = h[b];
 }
 
-__global__ __launch_bounds__(256) void k_fm_coef_reduce(FmArgs a, int nblocks, double seed,
-                                                        double* gp, double* gr, double* ge) {
+// Sum of the kFmBlocks block histograms in two stages (integer sums: any
+// order gives the same bits).  Stage 1: workgroup (x, y) sums, for 64
+// consecutive bins, the histograms of blocks y, y + kFmSplit, ... with its
+// four rows of 64 lanes taking every fourth of them (coalesced over the bins);
+// stage 2 adds the kFmSplit partial sums of each bin.
+__global__ __launch_bounds__(256) void k_fm_coef_reduce1(FmArgs a, int nblocks) {
+  __shared__ unsigned long long s_acc[4][64];
+  const int nb = a.nb_phi + a.nb_rho + a.nb_emb;
+  const int lane = (int)threadIdx.x & 63, row = (int)threadIdx.x >> 6;
+  const int b = blockIdx.x * 64 + lane;
+  unsigned long long acc = 0ull;
+  if (b < nb)
+    for (int k = (int)blockIdx.y + kFmSplit * row; k < nblocks; k += 4 * kFmSplit)
+      acc += a.hist[(int64_t)k * nb + b];
+  s_acc[row][lane] = acc;
+  __syncthreads();
+  if (row == 0 && b < nb)
+    a.part[(int64_t)blockIdx.y * nb + b] = ((s_acc[0][lane] + s_acc[1][lane]) + s_acc[2][lane]) +
+                                           s_acc[3][lane];
+}
+
+__global__ __launch_bounds__(256) void k_fm_coef_reduce(FmArgs a, double seed, double* gp,
+                                                        double* gr, double* ge) {
   const int nb = a.nb_phi + a.nb_rho + a.nb_emb;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   unsigned long long acc = 0ull;
-  for (int k = 0; k < nblocks; ++k) acc += a.hist[(int64_t)k * nb + b];
+  for (int k = 0; k < kFmSplit; ++k) acc += a.part[(int64_t)k * nb + b];
   const double v = seed * ((double)(long long)acc * a.scale[1]);
   if (b < a.nb_phi) gp[b] = v;
   else if (b < a.nb_phi + a.nb_rho) gr[b - a.nb_phi] = v;
@@ -415,6 +439,7 @@ size_t fm_part_bytes(char* base, int64_t n, int64_t tiles, int nbins, FmArgs* a)
   o.loss = c.take<double>(1);
   o.flag = c.take<int32_t>(1);
   o.hist = c.take<unsigned long long>((size_t)kFmBlocks * nbins);
+  o.part = c.take<unsigned long long>((size_t)kFmSplit * nbins);
   return (c.off + 255) & ~size_t(255);
 }
 
@@ -459,6 +484,8 @@ md_status md_fm_workspace_size(int32_t n_cfg, const int64_t* cfg_atoms, const do
   }
   tiles = ((tiles + kXcd - 1) / kXcd) * kXcd;
   const int nbins = 4 * ((n_knots[0] - 1) + (n_knots[1] - 1) + (n_knots[2] - 1));
+  // one histogram of all coefficient bins must fit the coefficient pass's LDS
+  if ((size_t)nbins * sizeof(unsigned long long) > kFmLds) return MD_E_TABLE;
   *bytes = ((mb + 255) & ~size_t(255)) + fm_part_bytes(nullptr, n, tiles, nbins, nullptr);
   return MD_OK;
 }
@@ -582,8 +609,11 @@ md_status md_fm_backward(md_fm_ctx* c, double seed, double* g_phi, double* g_rho
   hipLaunchKernelGGL(k_fm_coef, dim3(kFmBlocks), dim3(64), nb * sizeof(unsigned long long),
                      c->stream, a);
   FMC(c, hipGetLastError());
-  hipLaunchKernelGGL(k_fm_coef_reduce, dim3((nb + 255) / 256), dim3(256), 0, c->stream, a,
-                     kFmBlocks, seed, g_phi, g_rho, g_emb);
+  hipLaunchKernelGGL(k_fm_coef_reduce1, dim3((nb + 63) / 64, kFmSplit), dim3(256), 0, c->stream,
+                     a, kFmBlocks);
+  FMC(c, hipGetLastError());
+  hipLaunchKernelGGL(k_fm_coef_reduce, dim3((nb + 255) / 256), dim3(256), 0, c->stream, a, seed,
+                     g_phi, g_rho, g_emb);
   FMC(c, hipGetLastError());
   int32_t flag = 0;
   FMC(c, hipMemcpyAsync(&flag, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));

@@ -157,3 +157,26 @@ def test_launch_mode_validation_without_gpu(launch, mode, nt, ok):
     rc = lib.md_workspace_size(ctypes.byref(p), 1, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.byref(out))
     assert (rc == 0) == ok
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+@pytest.mark.parametrize("knots,ok", [((64, 64, 64), True), ((600, 600, 600), True),
+                                      ((700, 700, 700), False)])
+def test_fm_table_size_limit_without_gpu(knots, ok):
+    """The force-matching coefficient histogram (4 bins per segment, 8 bytes
+    each, all three tables) must fit 64 KB of LDS."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    lib.md_fm_workspace_size.restype = ctypes.c_int32
+    n = (ctypes.c_int64 * 1)(2000)
+    b = np.array([33.04, 33.04, 33.04])
+    nk = (ctypes.c_int32 * 3)(*knots)
+    out = ctypes.c_size_t(0)
+    rc = lib.md_fm_workspace_size(1, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.c_double(5.0), 128, nk, ctypes.byref(out))
+    assert (rc == 0) == ok, rc
+    if not ok:
+        assert rc == -3
