@@ -34,7 +34,7 @@ using namespace mdk;
 
 namespace {
 
-constexpr int kFmBlocks = 512;  // persistent blocks of the coefficient pass
+constexpr int kFmBlocks = 2048;  // blocks of the coefficient pass (8 waves per CU)
 constexpr int kFmSplit = 16;    // first-stage groups of block histograms in the reduction
 constexpr size_t kFmLds = 65536;  // LDS of the coefficient pass's histogram
 
