@@ -114,6 +114,12 @@ __device__ __forceinline__ void sep(const RepDev& rp, uint32_t e, const double4&
   dz += (double)((int)(code >> 4) - 1) * rp.box[2];
 }
 
+// The pair loops below take kFmBatch list entries at a time: all their list
+// loads, then all their neighbour loads, then the arithmetic in list order (so
+// every sum keeps its order).  Entries past the list end read the atom itself
+// and are skipped.
+constexpr int kFmBatch = 4;
+
 // rho_i, F'(rho_i), F''(rho_i)
 __global__ __launch_bounds__(64) void k_fm_density(FmArgs a) {
   const AtomTile tl = a.g.atiles[blockIdx.x];
@@ -123,12 +129,22 @@ __global__ __launch_bounds__(64) void k_fm_density(FmArgs a) {
   const double4 pi = a.s.pos[i];
   const int m = min(a.s.cnt[i], a.g.nbr_cap);
   double acc = 0.0;
-  for (int k = 0; k < m; ++k) {
-    const uint32_t e = a.s.nbr[(int64_t)k * a.g.n + i];
-    double dx, dy, dz;
-    sep(rp, e, pi, a.s.pos[e & kIndexMask], dx, dy, dz);
-    const double r2 = (dx * dx + dy * dy) + dz * dz;
-    if (r2 < a.rc2) acc += sp_f(a.rho, sqrt(r2));
+  for (int k0 = 0; k0 < m; k0 += kFmBatch) {
+    uint32_t e[kFmBatch];
+    double4 pj[kFmBatch];
+#pragma unroll
+    for (int u = 0; u < kFmBatch; ++u)
+      e[u] = (k0 + u < m) ? a.s.nbr[(int64_t)(k0 + u) * a.g.n + i] : (uint32_t)i;
+#pragma unroll
+    for (int u = 0; u < kFmBatch; ++u) pj[u] = a.s.pos[e[u] & kIndexMask];
+#pragma unroll
+    for (int u = 0; u < kFmBatch; ++u) {
+      if (k0 + u >= m) continue;
+      double dx, dy, dz;
+      sep(rp, e[u], pi, pj[u], dx, dy, dz);
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      if (r2 < a.rc2) acc += sp_f(a.rho, sqrt(r2));
+    }
   }
   a.rho_i[i] = acc;
   a.fp[i] = sp_df(a.emb, acc);
@@ -146,18 +162,32 @@ __global__ __launch_bounds__(64) void k_fm_force(FmArgs a) {
     const double4 pi = a.s.pos[i];
     const int m = min(a.s.cnt[i], a.g.nbr_cap);
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int k = 0; k < m; ++k) {
-      const uint32_t e = a.s.nbr[(int64_t)k * a.g.n + i];
-      const uint32_t j = e & kIndexMask;
-      double dx, dy, dz;
-      sep(rp, e, pi, a.s.pos[j], dx, dy, dz);
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      if (r2 < a.rc2) {
-        const double r = sqrt(r2);
-        const double sc = (a.fp[i] + a.fp[j]) * sp_df(a.rho, r) + sp_df(a.phi, r);
-        fx += sc * dx / r;
-        fy += sc * dy / r;
-        fz += sc * dz / r;
+    const double fpi = a.fp[i];
+    for (int k0 = 0; k0 < m; k0 += kFmBatch) {
+      uint32_t e[kFmBatch];
+      double4 pj[kFmBatch];
+      double fpj[kFmBatch];
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u)
+        e[u] = (k0 + u < m) ? a.s.nbr[(int64_t)(k0 + u) * a.g.n + i] : (uint32_t)i;
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u) {
+        pj[u] = a.s.pos[e[u] & kIndexMask];
+        fpj[u] = a.fp[e[u] & kIndexMask];
+      }
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u) {
+        if (k0 + u >= m) continue;
+        double dx, dy, dz;
+        sep(rp, e[u], pi, pj[u], dx, dy, dz);
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (r2 < a.rc2) {
+          const double r = sqrt(r2);
+          const double sc = (fpi + fpj[u]) * sp_df(a.rho, r) + sp_df(a.phi, r);
+          fx += sc * dx / r;
+          fy += sc * dy / r;
+          fz += sc * dz / r;
+        }
       }
     }
     const double4 fr = a.fref[i];
@@ -203,18 +233,33 @@ __global__ __launch_bounds__(64) void k_fm_lambda(FmArgs a) {
     const double4 gi = a.gvec[i];
     const int m = min(a.s.cnt[i], a.g.nbr_cap);
     double acc = 0.0, fpmax = 0.0;
-    for (int k = 0; k < m; ++k) {
-      const uint32_t e = a.s.nbr[(int64_t)k * a.g.n + i];
-      const uint32_t j = e & kIndexMask;
-      double dx, dy, dz;
-      sep(rp, e, pi, a.s.pos[j], dx, dy, dz);
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      if (r2 < a.rc2) {
-        const double r = sqrt(r2);
-        const double4 gj = a.gvec[j];
-        const double sij = ((gi.x - gj.x) * dx + (gi.y - gj.y) * dy + (gi.z - gj.z) * dz) / r;
-        acc += sij * sp_df(a.rho, r);
-        fpmax = fmax(fpmax, fabs(a.fp[j]));
+    for (int k0 = 0; k0 < m; k0 += kFmBatch) {
+      uint32_t e[kFmBatch];
+      double4 pj[kFmBatch], gj[kFmBatch];
+      double fpj[kFmBatch];
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u)
+        e[u] = (k0 + u < m) ? a.s.nbr[(int64_t)(k0 + u) * a.g.n + i] : (uint32_t)i;
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u) {
+        const uint32_t j = e[u] & kIndexMask;
+        pj[u] = a.s.pos[j];
+        gj[u] = a.gvec[j];
+        fpj[u] = a.fp[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u) {
+        if (k0 + u >= m) continue;
+        double dx, dy, dz;
+        sep(rp, e[u], pi, pj[u], dx, dy, dz);
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (r2 < a.rc2) {
+          const double r = sqrt(r2);
+          const double sij =
+              ((gi.x - gj[u].x) * dx + (gi.y - gj[u].y) * dy + (gi.z - gj[u].z) * dz) / r;
+          acc += sij * sp_df(a.rho, r);
+          fpmax = fmax(fpmax, fabs(fpj[u]));
+        }
       }
     }
     const double mu = acc * a.fpp[i];
@@ -293,31 +338,44 @@ __global__ __launch_bounds__(64) void k_fm_coef(FmArgs a) {
     const double4 gi = a.gvec[i];
     const double fpi = a.fp[i], mui = a.mu[i];
     const int m = min(a.s.cnt[i], a.g.nbr_cap);
-    for (int k = 0; k < m; ++k) {
-      const uint32_t e = a.s.nbr[(int64_t)k * a.g.n + i];
-      const uint32_t j = e & kIndexMask;
-      double dx, dy, dz;
-      sep(rp, e, pi, a.s.pos[j], dx, dy, dz);
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      if (!(r2 < a.rc2)) continue;
-      const double r = sqrt(r2);
-      const double w = (gi.x * dx + gi.y * dy + gi.z * dz) / r;
-      int kp;
-      double tp;
-      seg(a.phi, r, kp, tp);
-      const double ap = a.phi.inv_dx;
-      fix_add(hp, 4 * kp + 1, w * ap, S, a.flag);
-      fix_add(hp, 4 * kp + 2, w * 2.0 * tp * ap, S, a.flag);
-      fix_add(hp, 4 * kp + 3, w * 3.0 * tp * tp * ap, S, a.flag);
-      int kr;
-      double tr;
-      seg(a.rho, r, kr, tr);
-      const double ar = a.rho.inv_dx;
-      const double wf = w * (fpi + a.fp[j]);
-      fix_add(hr, 4 * kr + 0, mui, S, a.flag);
-      fix_add(hr, 4 * kr + 1, wf * ar + mui * tr, S, a.flag);
-      fix_add(hr, 4 * kr + 2, wf * 2.0 * tr * ar + mui * tr * tr, S, a.flag);
-      fix_add(hr, 4 * kr + 3, wf * 3.0 * tr * tr * ar + mui * tr * tr * tr, S, a.flag);
+    for (int k0 = 0; k0 < m; k0 += kFmBatch) {
+      uint32_t e[kFmBatch];
+      double4 pj[kFmBatch];
+      double fpj[kFmBatch];
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u)
+        e[u] = (k0 + u < m) ? a.s.nbr[(int64_t)(k0 + u) * a.g.n + i] : (uint32_t)i;
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u) {
+        pj[u] = a.s.pos[e[u] & kIndexMask];
+        fpj[u] = a.fp[e[u] & kIndexMask];
+      }
+#pragma unroll
+      for (int u = 0; u < kFmBatch; ++u) {
+        if (k0 + u >= m) break;
+        double dx, dy, dz;
+        sep(rp, e[u], pi, pj[u], dx, dy, dz);
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (!(r2 < a.rc2)) continue;
+        const double r = sqrt(r2);
+        const double w = (gi.x * dx + gi.y * dy + gi.z * dz) / r;
+        int kp;
+        double tp;
+        seg(a.phi, r, kp, tp);
+        const double ap = a.phi.inv_dx;
+        fix_add(hp, 4 * kp + 1, w * ap, S, a.flag);
+        fix_add(hp, 4 * kp + 2, w * 2.0 * tp * ap, S, a.flag);
+        fix_add(hp, 4 * kp + 3, w * 3.0 * tp * tp * ap, S, a.flag);
+        int kr;
+        double tr;
+        seg(a.rho, r, kr, tr);
+        const double ar = a.rho.inv_dx;
+        const double wf = w * (fpi + fpj[u]);
+        fix_add(hr, 4 * kr + 0, mui, S, a.flag);
+        fix_add(hr, 4 * kr + 1, wf * ar + mui * tr, S, a.flag);
+        fix_add(hr, 4 * kr + 2, wf * 2.0 * tr * ar + mui * tr * tr, S, a.flag);
+        fix_add(hr, 4 * kr + 3, wf * 3.0 * tr * tr * ar + mui * tr * tr * tr, S, a.flag);
+      }
     }
     int ke;
     double te;
