@@ -144,6 +144,11 @@ typedef struct md_stats_t {
  * n_rep replicas; rep_atoms[r] atoms and orthorhombic box rep_box[3r..3r+2]
  * (A) for replica r (host arrays).
  *
+ * Sizes: n_rep >= 1 and every replica holds at least one atom (an empty one
+ * is MD_E_ARG).  All replicas together hold fewer than 2^26 atoms (the list
+ * keeps a 26-bit atom index), and atoms x nbr_capacity x 4 bytes of list stay
+ * below 2^32 (8,388,607 atoms at capacity 128); larger sizes are MD_E_ARG.
+ *
  * Box convention: a positive length L makes that dimension periodic on
  * [0, L).  A negative length -E makes it open (free surfaces, as on the
  * lateral faces of the paper's slab, Sec. IV): no wrap and no image; E is the
@@ -205,7 +210,8 @@ md_status md_build_neighbors(md_ctx* ctx);
  * rebuilt on the device in the step after any atom moved more than skin/2.
  * Whole chunks run as one captured hipGraph.  On an error the state rolls
  * back to the start of the chunk in which it occurred (the status is
- * returned; md_stats().steps tells where). */
+ * returned; md_stats().steps tells where).  n = 0 takes no step and returns
+ * the latched status; n < 0 is MD_E_ARG. */
 md_status md_step(md_ctx* ctx, int64_t n);
 
 /* Potential and kinetic energy per replica (host arrays of n_rep doubles;

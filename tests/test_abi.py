@@ -180,3 +180,53 @@ def test_fm_table_size_limit_without_gpu(knots, ok):
     assert (rc == 0) == ok, rc
     if not ok:
         assert rc == -3
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+@pytest.mark.parametrize("atoms,cap,ok", [
+    ((1,), 128, True),                      # the smallest system
+    ((0,), 128, False),                     # an empty replica
+    ((500, 0, 500), 128, False),            # an empty replica inside a batch
+    ((-3,), 128, False),
+    ((8_388_607,), 128, True),              # the largest list at capacity 128
+    ((8_388_608,), 128, False),             # 2^32 bytes of list
+    ((4_194_304, 4_194_304), 128, False),   # the same, over two replicas
+    ((67_108_863,), 16, True),              # the largest atom index
+    ((67_108_864,), 8, False),              # 2^26 atoms
+])
+def test_size_limits_without_gpu(atoms, cap, ok):
+    """md_workspace_size checks the sizes on the host: at least one atom per
+    replica, fewer than 2^26 atoms (26-bit list index) and below 2^32 bytes of
+    list."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0, nbr_capacity=cap)
+    n = (ctypes.c_int64 * len(atoms))(*atoms)
+    b = np.tile(np.array([400.0, 400.0, 400.0]), len(atoms))
+    out = ctypes.c_size_t(0)
+    rc = lib.md_workspace_size(ctypes.byref(p), len(atoms), n,
+                               b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(out))
+    assert (rc == 0) == ok, rc
+    if not ok:
+        assert rc == -1
+    else:
+        assert out.value >= 4 * cap * sum(atoms)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+def test_no_replicas_without_gpu():
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0)
+    n = (ctypes.c_int64 * 1)(100)
+    b = np.array([20.0, 20.0, 20.0])
+    out = ctypes.c_size_t(0)
+    rc = lib.md_workspace_size(ctypes.byref(p), 0, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(out))
+    assert rc == -1
