@@ -134,6 +134,43 @@ def test_hot_run_rebuilds_and_matches(md, tabs, oracle_lib):
     s.close()
 
 
+def test_calls_between_steps_keep_the_trajectory(md, tabs, oracle_lib):
+    """A hot box rebuilds every few steps; list builds, binning passes, the
+    step's own kernels as timing passes, energy and force evaluations between
+    short step calls (eager steps and graph chunks) leave the oracle trajectory
+    unchanged, also when a rebuild is already due at the next step."""
+    box = configs.small_box(8, seed=42, temperature=6000.0, sigma_x=0.05)
+    _say(f"[gpu] calls between steps n={box.n}")
+    s = _system(md, tabs, box, chunk_steps=20)
+    s.build_neighbors()
+    calls = [
+        lambda: s.launch_pass(md.PASS_BUILD, 1),
+        lambda: s.energy(),
+        lambda: s.launch_pass(md.PASS_BIN, 2),
+        lambda: s.compute_forces(),
+        lambda: s.launch_pass(md.PASS_DENSITY, 2),
+        lambda: s.launch_pass(md.PASS_FORCE, 1),
+    ]
+    total = 0
+    for k in range(12):
+        n = 20 if k % 4 == 3 else 3 + (k % 3)
+        s.step(n)
+        total += n
+        calls[k % len(calls)]()
+    x, v, f = s.get_state()
+    st = s.stats()
+    s.close()
+    out = oracle_lib.md_run(box.x, box.v, box.box, tabs, total, mass=configs.MASS, dt=configs.DT,
+                            r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+    assert out["code"] == 0
+    d = x.cpu().numpy() - out["x"]
+    d -= box.box * np.round(d / box.box)
+    assert np.max(np.abs(d)) < 1e-9
+    assert np.max(np.abs(v.cpu().numpy() - out["v"])) < 1e-10
+    # the list builds between calls reset the skin reference, so fewer fall due in md_step
+    assert st["steps"] == total and st["rebuilds"] >= 8
+
+
 def test_bitwise_repeatable(md, tabs):
     box = configs.small_box(10, seed=51, temperature=1500.0)
     _say(f"[gpu] determinism n={box.n}")
