@@ -283,7 +283,9 @@ md_status md_fm_workspace_size(int32_t n_cfg, const int64_t* cfg_atoms, const do
 
 /* x and fref: device [n][3] float64 (all configs concatenated).  The knot
  * grids (x0, inv_dx, n_knots) of the three tables are fixed here; their
- * coefficients are passed to each forward call. */
+ * coefficients are passed to each forward call.  The context keeps 16 bytes
+ * of pinned host memory (hipHostMalloc) for the scalars the calls return,
+ * freed by md_fm_destroy. */
 md_status md_fm_create(md_fm_ctx** out, int32_t n_cfg, const int64_t* cfg_atoms,
                        const double* cfg_box, double r_cut, int32_t nbr_capacity,
                        const md_spline* grid_phi, const md_spline* grid_rho,

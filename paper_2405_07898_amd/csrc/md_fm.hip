@@ -494,8 +494,9 @@ size_t fm_part_bytes(char* base, int64_t n, int64_t tiles, int nbins, FmArgs* a)
   o.partial = c.take<double>((size_t)tiles);
   o.bound = c.take<double>((size_t)tiles);
   o.scale = c.take<double>(2);
-  o.loss = c.take<double>(1);
-  o.flag = c.take<int32_t>(1);
+  // the loss and the flag word side by side: the forward returns both with one copy
+  o.loss = c.take<double>(2);
+  o.flag = o.loss ? reinterpret_cast<int32_t*>(o.loss + 1) : nullptr;
   o.hist = c.take<unsigned long long>((size_t)kFmBlocks * nbins);
   o.part = c.take<unsigned long long>((size_t)kFmSplit * nbins);
   return (c.off + 255) & ~size_t(255);
@@ -511,6 +512,7 @@ struct md_fm_ctx {
   hipStream_t stream = nullptr;
   int64_t n = 0;
   bool have_forward = false;
+  double* host = nullptr;  // pinned: the loss and the flag word copied back
   std::string err;
 };
 
@@ -615,10 +617,15 @@ md_status md_fm_create(md_fm_ctx** out, int32_t n_cfg, const int64_t* cfg_atoms,
   hipLaunchKernelGGL(k_fm_import_ref, dim3(c->v.L.atile_blocks), dim3(64), 0, c->stream, a, fref);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  const char* what = "import fref";
+  if (e == hipSuccess) {
+    what = "hipHostMalloc";
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->host), 2 * sizeof(double));
+  }
   if (e != hipSuccess) {
     md_destroy(c->md);
     delete c;
-    return fm_fail(nullptr, e, "import fref");
+    return fm_fail(nullptr, e, what);
   }
   *out = c;
   return MD_OK;
@@ -643,12 +650,12 @@ md_status md_fm_forward(md_fm_ctx* c, const double* coef_phi, const double* coef
     hipLaunchKernelGGL(k_fm_export_f, dim3(tb), dim3(64), 0, c->stream, a, f_out);
     FMC(c, hipGetLastError());
   }
-  double l = 0.0;
-  int32_t flag = 0;
-  FMC(c, hipMemcpyAsync(&l, a.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  FMC(c, hipMemcpyAsync(&flag, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  FMC(c, hipMemcpyAsync(c->host, a.loss, sizeof(double) + sizeof(int32_t),
+                        hipMemcpyDeviceToHost, c->stream));
   FMC(c, hipStreamSynchronize(c->stream));
-  if (loss) *loss = l;
+  int32_t flag = 0;
+  memcpy(&flag, c->host + 1, sizeof(int32_t));
+  if (loss) *loss = c->host[0];
   c->have_forward = true;
   return flag ? MD_E_NONFINITE : MD_OK;
 }
@@ -673,15 +680,17 @@ md_status md_fm_backward(md_fm_ctx* c, double seed, double* g_phi, double* g_rho
   hipLaunchKernelGGL(k_fm_coef_reduce, dim3((nb + 255) / 256), dim3(256), 0, c->stream, a, seed,
                      g_phi, g_rho, g_emb);
   FMC(c, hipGetLastError());
-  int32_t flag = 0;
-  FMC(c, hipMemcpyAsync(&flag, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  FMC(c, hipMemcpyAsync(c->host + 1, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   FMC(c, hipStreamSynchronize(c->stream));
+  int32_t flag = 0;
+  memcpy(&flag, c->host + 1, sizeof(int32_t));
   return flag ? MD_E_NONFINITE : MD_OK;
 }
 
 void md_fm_destroy(md_fm_ctx* c) {
   if (!c) return;
   if (c->md) md_destroy(c->md);
+  if (c->host) (void)hipHostFree(c->host);
   delete c;
 }
 
