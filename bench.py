@@ -453,6 +453,8 @@ def main() -> int:
     ap.add_argument("--sequential-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM counters)")
+    ap.add_argument("--fm-only", action="store_true",
+                    help="time only the force-matching gradient (one JSON object, for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the EAM path here is built and timed on a "
@@ -468,6 +470,10 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     md.lib()
     tabs = potential.md_tables()
+    if args.fm_only:
+        print(json.dumps({"force_matching": bench_fm(torch, md, configs, potential, tabs)}),
+              flush=True)
+        return 0
     box = configs.config_128k()
     log(f"workload 128k: n={box.n} box={box.box[0]:.3f} A; building")
     s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100, lpa=args.lpa)
