@@ -66,11 +66,11 @@ class SplineTable:
         return self.x0 + (self.n_knots - 1) * self.dx
 
 
-SPEC = dict(phi_a=PHI_A, well_w=WELL_W, emb_a=EMB_A)
+SPECIFIED = dict(phi_a=PHI_A, well_w=WELL_W, emb_a=EMB_A)
 STABLE = dict(phi_a=1.5514, well_w=0.14, emb_a=3.0)
 
 
-def analytic_params(p: dict = SPEC) -> dict:
+def analytic_params(p: dict = SPECIFIED) -> dict:
     """All constants of a parameter set, for evaluators of the closed forms."""
     return dict(rc=RC, r0=R0, phi_a=p["phi_a"], phi_b=PHI_B, rho_b=RHO_B, emb_a=p["emb_a"],
                 well_w=p["well_w"], well_s=WELL_S, well_r=WELL_R)
@@ -103,32 +103,32 @@ def _dpair_core(r, p):
             + p["well_w"] * (2.0 * u / WELL_S) * np.exp(-u ** 2))
 
 
-def phi(r, p=SPEC):
+def phi(r, p=SPECIFIED):
     return _pair_core(r, p) * fc(r)
 
 
-def dphi(r, p=SPEC):
+def dphi(r, p=SPECIFIED):
     return _dpair_core(r, p) * fc(r) + _pair_core(r, p) * dfc(r)
 
 
-def rho(r, p=SPEC):
+def rho(r, p=SPECIFIED):
     return np.exp(-RHO_B * (np.asarray(r) / R0 - 1.0)) * fc(r)
 
 
-def drho(r, p=SPEC):
+def drho(r, p=SPECIFIED):
     e = np.exp(-RHO_B * (np.asarray(r) / R0 - 1.0))
     return e * (-RHO_B / R0) * fc(r) + e * dfc(r)
 
 
-def emb(x, p=SPEC):
+def emb(x, p=SPECIFIED):
     return -p["emb_a"] * np.sqrt(np.asarray(x, dtype=np.float64))
 
 
-def demb(x, p=SPEC):
+def demb(x, p=SPECIFIED):
     return -0.5 * p["emb_a"] / np.sqrt(np.asarray(x, dtype=np.float64))
 
 
-def ddemb(x, p=SPEC):
+def ddemb(x, p=SPECIFIED):
     return 0.25 * p["emb_a"] * np.asarray(x, dtype=np.float64) ** -1.5
 
 
@@ -155,7 +155,7 @@ def tabulate(fn, x1: float, n_knots: int) -> SplineTable:
     return natural_spline_from_values(0.0, dx, fn(xs))
 
 
-def md_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX, p: dict = SPEC):
+def md_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX, p: dict = SPECIFIED):
     """(phi, rho, F) tables used by every MD workload: phi, rho on [0, rc], F on [0, rho_max]."""
     return (tabulate(lambda r: phi(r, p), RC, n_knots), tabulate(lambda r: rho(r, p), RC, n_knots),
             tabulate(lambda x: emb(x, p), rho_max, n_knots))
