@@ -217,6 +217,39 @@ def test_density_past_the_f_table(md, tabs, oracle_lib):
     s.close()
 
 
+def test_maximum_capacities(md, tabs, oracle_lib):
+    """Both capacities at their documented maxima (nbr_capacity 1024,
+    cell_capacity 256): a lattice compressed to a = 1.5 A holds up to ~140
+    atoms per cell and ~340 list entries per atom, so a cell's ~3,500
+    candidates are staged in 14 batches.  Cells and neighbour sets bit-exact, forces 1e-10,
+    a short trajectory 1e-9 A."""
+    box = configs.small_box(12, seed=56, a=1.5, sigma_x=0.01)
+    _say(f"[gpu] maximum capacities n={box.n}")
+    s = _system(md, tabs, box, nbr_capacity=1024, cell_capacity=256, chunk_steps=10)
+    s.build_neighbors()
+    st = s.stats()
+    assert 64 < st["max_cell"] <= 256 and 300 < st["max_list"] <= 1024
+    cell_gpu = s.cells().cpu().numpy()
+    cell_o, _, _ = oracle_lib.cell_ids(box.x, box.box, RC + SKIN)
+    assert np.array_equal(cell_gpu, cell_o)
+    cnt_g, nbr_g = (t.cpu().numpy() for t in s.neighbors(1024))
+    cnt_o, nbr_o, _ = oracle_lib.neighbor_list(box.x, box.box, RC + SKIN, cap=1024)
+    assert np.array_equal(cnt_g, cnt_o)
+    assert oracle_lib.neighbor_sets(cnt_g, nbr_g) == oracle_lib.neighbor_sets(cnt_o, nbr_o)
+    f, _, _ = s.compute_forces()
+    ref = oracle_lib.forces_at(box.x, box.box, tabs, RC, SKIN, cap=1024)
+    assert _rel(f.cpu().numpy(), ref["f"]) < 1e-10
+    s.step(10)
+    x, _, _ = s.get_state()
+    s.close()
+    out = oracle_lib.md_run(box.x, box.v, box.box, tabs, 10, mass=configs.MASS, dt=configs.DT,
+                            r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V, cap=1024)
+    assert out["code"] == 0
+    d = x.cpu().numpy() - out["x"]
+    d -= box.box * np.round(d / box.box)
+    assert np.max(np.abs(d)) < 1e-9
+
+
 def test_error_paths(md, tabs):
     box = configs.small_box(6, seed=53)
     _say("[gpu] error paths")
