@@ -59,6 +59,7 @@ CASES = [
                                                    sigma_x=0.05, temperature=900.0)),
     ("min_3cells", lambda: configs.small_box(5, seed=32, sigma_x=0.2, temperature=300.0)),
     ("hot_12cells", lambda: configs.small_box(12, seed=33, sigma_x=0.25, temperature=2500.0)),
+    ("ortho_5x6x7", lambda: configs.ortho_box(5, 6, 7, seed=36, sigma_x=0.1, temperature=900.0)),
 ]
 
 
@@ -132,6 +133,27 @@ def test_hot_run_rebuilds_and_matches(md, tabs, oracle_lib):
     fr = oracle_lib.forces_at(x.cpu().numpy(), box.box, tabs, RC, SKIN)
     assert _rel(f.cpu().numpy(), fr["f"]) < 1e-10
     s.close()
+
+
+def test_orthorhombic_hot_run(md, tabs, oracle_lib):
+    """Three different periodic edge lengths, hot enough to cross the faces and
+    rebuild: the oracle trajectory."""
+    box = configs.ortho_box(5, 6, 7, seed=37, sigma_x=0.05, temperature=3000.0)
+    _say(f"[gpu] orthorhombic hot run n={box.n} box={box.box.tolist()}")
+    s = _system(md, tabs, box, chunk_steps=20)
+    s.build_neighbors()
+    s.step(61)
+    x, v, _ = s.get_state()
+    st = s.stats()
+    s.close()
+    out = oracle_lib.md_run(box.x, box.v, box.box, tabs, 61, mass=configs.MASS, dt=configs.DT,
+                            r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+    assert out["code"] == 0
+    d = x.cpu().numpy() - out["x"]
+    d -= box.box * np.round(d / box.box)
+    assert np.max(np.abs(d)) < 1e-9
+    assert np.max(np.abs(v.cpu().numpy() - out["v"])) < 1e-10
+    assert st["rebuilds"] >= 2
 
 
 def test_calls_between_steps_keep_the_trajectory(md, tabs, oracle_lib):

@@ -159,6 +159,39 @@ def test_neighbor_list_brute_pairs_by_numpy(oracle_lib):
     assert got == want
 
 
+@pytest.mark.parametrize("method", ["cells", "brute"])
+def test_orthorhombic_lists_by_numpy(oracle_lib, method):
+    """Three different periodic edge lengths: both list builders against numpy
+    all-pairs distances under the minimum image of each dimension."""
+    b = configs.ortho_box(5, 6, 7, seed=6, sigma_x=0.3)
+    assert len(set(b.box.tolist())) == 3
+    cnt, nbr, _ = oracle_lib.neighbor_list(b.x, b.box, RC + SKIN, method=method)
+    d = b.x[None, :, :] - b.x[:, None, :]
+    d -= b.box * np.round(d / b.box)
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    assert not (np.abs(r - (RC + SKIN)) < 1e-9).any()
+    want = [frozenset(np.nonzero(r[i] < RC + SKIN)[0].tolist()) for i in range(b.n)]
+    assert oracle_lib.neighbor_sets(cnt, nbr) == want
+
+
+def test_orthorhombic_forces_are_negative_energy_gradient(oracle_lib, md_tables):
+    """Central differences of the energy for atoms next to each periodic face."""
+    b = configs.ortho_box(5, 6, 7, seed=7, sigma_x=0.1)
+    res = oracle_lib.forces_at(b.x, b.box, md_tables, RC, SKIN)
+    h = 1e-5
+    picks = [int(np.argmin(b.x[:, d])) for d in range(3)] + \
+            [int(np.argmax(b.x[:, d])) for d in range(3)]
+    for i in picks:
+        for d in range(3):
+            xp, xm = b.x.copy(), b.x.copy()
+            xp[i, d] += h
+            xm[i, d] -= h
+            ep = oracle_lib.forces_at(xp, b.box, md_tables, RC, SKIN)["pe"]
+            em = oracle_lib.forces_at(xm, b.box, md_tables, RC, SKIN)["pe"]
+            assert abs(-(ep - em) / (2 * h) - res["f"][i, d]) < 1e-5
+
+
 def test_cell_assignment_properties(oracle_lib):
     b = configs.small_box(10, seed=7, sigma_x=0.3)
     cell, nc, ic = oracle_lib.cell_ids(b.x, b.box, RC + SKIN)

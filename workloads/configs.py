@@ -149,6 +149,20 @@ def bcc_block(nx: int, ny: int, nz: int, a: float = A_LAT) -> np.ndarray:
     return ((base + basis[None]) * a).reshape(-1, 3)
 
 
+def ortho_box(nx: int, ny: int, nz: int, seed: int, *, sigma_x: float = 0.05,
+              temperature: float = 300.0, a: float = A_LAT) -> Box:
+    """A periodic BCC box of nx x ny x nz cells with three different edge
+    lengths (a cube cannot tell the x, y and z image lengths apart)."""
+    rng = np.random.default_rng(seed)
+    x = bcc_block(nx, ny, nz, a)
+    x = x + sigma_x * rng.standard_normal(x.shape)
+    box = np.array([nx * a, ny * a, nz * a])
+    x = np.mod(x, box)
+    v = maxwell_boltzmann(rng, x.shape[0], temperature)
+    return Box(x=x, v=v, box=box, n_cells=nx, temperature=temperature,
+               site_ids=np.arange(x.shape[0], dtype=np.int64))
+
+
 def slab(nx: int, ny: int, nz: int, seed: int, *, vacuum: float = 12.0,
          temperature: float = 300.0, sigma_x: float = 0.01, a: float = A_LAT) -> Box:
     """A thin BCC slab, open in x and y, periodic in z (the paper's geometry:
