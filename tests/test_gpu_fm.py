@@ -56,6 +56,29 @@ def test_loss_forces_gradient_match_oracle(fm, oracle_lib, n_cfg, ncell):
     prob.close()
 
 
+def test_orthorhombic_configurations(fm, oracle_lib):
+    """Configurations with three different periodic edge lengths (the adjoint
+    kernels apply image shifts of their own)."""
+    import torch
+
+    boxes = [configs.ortho_box(5, 6, 7, seed=120, sigma_x=0.1, temperature=0.0),
+             configs.ortho_box(7, 5, 6, seed=121, sigma_x=0.1, temperature=0.0)]
+    x, off, bx, fref = _problem(oracle_lib, boxes)
+    tabs = P.fm_tables()
+    _say(f"[gpu] force matching orthorhombic n={x.shape[0]}")
+    prob = fm.ForceMatch(x, fref, np.diff(off), bx, tabs)
+    coefs = [torch.as_tensor(t.coef, device="cuda") for t in tabs]
+    loss, f = prob.forward(*coefs, want_forces=True)
+    g = [t.cpu().numpy() for t in prob.backward()]
+    prob.close()
+    loss_o, g_o, f_o = oracle_lib.fm_loss_grad(x, off, bx, tabs, fref)
+    assert abs(loss - loss_o) <= 1e-12 * abs(loss_o)
+    assert np.max(np.abs(f.cpu().numpy() - f_o)) <= 1e-10 * np.max(np.abs(f_o))
+    scale = max(np.max(np.abs(a)) for a in g_o)
+    for a, b in zip(g, g_o):
+        assert np.max(np.abs(a - b)) <= 1e-9 * scale
+
+
 def test_adjoint_is_deterministic_and_autograd_consistent(fm, oracle_lib):
     import torch
 

@@ -134,3 +134,28 @@ def test_knot_value_chain_rule(oracle_lib, fm_problem):
             vals.append(_loss(oracle_lib, pb, (t0, pb["tabs"][1], pb["tabs"][2])))
         fd = (vals[0] - vals[1]) / 2e-6
         assert abs(fd - gy[k]) <= 1e-6 * np.max(np.abs(gy)), (k, fd, gy[k])
+
+
+def test_orthorhombic_configurations_by_central_difference(oracle_lib):
+    """Configurations with three different periodic edge lengths: the phi
+    gradient against central differences (exact up to rounding, the loss being
+    quadratic in those coefficients)."""
+    boxes = [configs.ortho_box(5, 6, 7, seed=110, sigma_x=0.12, temperature=0.0),
+             configs.ortho_box(6, 5, 5, seed=111, sigma_x=0.12, temperature=0.0)]
+    x = np.concatenate([b.x for b in boxes])
+    off = np.array([0, boxes[0].n, boxes[0].n + boxes[1].n], np.int64)
+    bx = np.stack([b.box for b in boxes])
+    fref = np.concatenate([oracle_lib.forces_analytic(b.x, b.box, P.analytic_params())[0]
+                           for b in boxes])
+    pb = dict(x=x, off=off, boxes=bx, fref=fref, tabs=P.fm_tables())
+    _, grads, _ = oracle_lib.fm_loss_grad(x, off, bx, pb["tabs"], fref)
+    g = grads[0].ravel()
+    nz = np.nonzero(g)[0]
+    pick = nz[np.argsort(-np.abs(g[nz]))[:8]]
+    h = 1e-6
+    loss0 = _loss(oracle_lib, pb, pb["tabs"])
+    tol = 8 * np.finfo(float).eps * loss0 / h
+    for q in pick:
+        lp = _loss(oracle_lib, pb, _with(pb["tabs"], 0, q, h))
+        lm = _loss(oracle_lib, pb, _with(pb["tabs"], 0, q, -h))
+        assert abs((lp - lm) / (2 * h) - g[q]) <= tol
