@@ -232,3 +232,36 @@ def test_multi_full_size_128k(md, atabs, oracle_lib):
     assert out["code"] == 0
     assert np.max(np.abs(_disp(x.cpu().numpy(), out["x"], box.box))) < 1e-9
     assert np.max(np.abs(v.cpu().numpy() - out["v"])) < 1e-11
+
+
+@pytest.mark.parametrize("nt", [3, 4])
+@pytest.mark.parametrize("lpa", [1, 4])
+def test_three_and_four_types(md, oracle_lib, nt, lpa):
+    """More than two types: the pair-table rows (one per unordered type pair),
+    density rows that no longer fit the LDS (read from global memory), and
+    force rows mostly outside the LDS window.  rho, F', forces and energy
+    against the oracle, then a hot 41-step trajectory with rebuilds."""
+    tabs = P.alloy_tables(n_types=nt)
+    masses = P.MULTI_MASS[:nt]
+    box = configs.multi_box(6, 80 + nt, masses, sigma_x=0.1, temperature=1500.0)
+    assert set(np.unique(box.types).tolist()) == set(range(nt))
+    _say(f"[gpu] {nt} types n={box.n} lpa={lpa}")
+    s = _system(md, tabs, box, masses=masses, n_types=nt, lanes_per_atom=lpa, chunk_steps=20)
+    s.build_neighbors()
+    f, rho, fp = s.compute_forces()
+    ref = oracle_lib.forces_at_multi(box.x, box.box, box.types, tabs, RC, SKIN)
+    assert _rel(rho.cpu().numpy(), ref["rho"]) < 1e-12
+    assert _rel(fp.cpu().numpy(), ref["fp"]) < 1e-12
+    assert _rel(f.cpu().numpy(), ref["f"]) < 1e-10
+    pe, _ = s.energy()
+    assert abs(pe[0] - ref["pe"]) <= 1e-12 * abs(ref["pe"])
+    s.step(41)
+    x, v, _ = s.get_state()
+    st = s.stats()
+    s.close()
+    out = oracle_lib.md_run_multi(box.x, box.v, box.box, box.types, tabs, masses, 41,
+                                  dt=configs.DT, r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+    assert out["code"] == 0
+    assert np.max(np.abs(_disp(x.cpu().numpy(), out["x"], box.box))) < 1e-9
+    assert np.max(np.abs(v.cpu().numpy() - out["v"])) < 1e-11
+    assert st["rebuilds"] >= 1

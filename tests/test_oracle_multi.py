@@ -106,3 +106,58 @@ def test_alloy_nve_second_order_and_momentum(oracle_lib, alloy_tabs):
     # below 1e-4 of the total and falls 4x when dt halves
     assert errs[0] < 1e-4 * abs(e0)
     assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+@pytest.fixture(scope="module")
+def tabs3():
+    return P.alloy_tables(n_types=3)
+
+
+@pytest.mark.parametrize("pair", [(0, 2), (2, 1), (2, 2)])
+def test_three_type_dimer_closed_form(oracle_lib, tabs3, pair):
+    """A third type: energy and force of a dimer against the closed forms (the
+    same bound as the binary dimers' tables)."""
+    a, b = pair
+    r = 2.5
+    x = np.array([[6.0, 6.0, 6.0], [6.0 + r, 6.0, 6.0]])
+    res = oracle_lib.forces_at_multi(x, np.full(3, 20.0), [a, b], tabs3, RC, SKIN)
+    e = P.alloy_phi(r, a, b) + P.alloy_emb(P.alloy_rho(r, b), a) + P.alloy_emb(P.alloy_rho(r, a), b)
+    s = (P.alloy_dphi(r, a, b) + P.alloy_demb(P.alloy_rho(r, b), a) * P.alloy_drho(r, b)
+         + P.alloy_demb(P.alloy_rho(r, a), b) * P.alloy_drho(r, a))
+    assert abs(res["pe"] - e) < 1e-6
+    np.testing.assert_allclose(res["rho"], [P.alloy_rho(r, b), P.alloy_rho(r, a)], rtol=1e-7)
+    np.testing.assert_allclose(res["f"][0], [s, 0, 0], atol=1e-4)
+    np.testing.assert_allclose(res["f"][1], [-s, 0, 0], atol=1e-4)
+
+
+def test_three_types_relabelled_by_a_cycle(oracle_lib, tabs3):
+    """Relabelling the types by the cycle 0 -> 1 -> 2 -> 0, with the tables
+    permuted to match, changes no bit."""
+    phi, rho, emb = tabs3
+    perm = [1, 2, 0]  # new label of old type t
+    inv = [2, 0, 1]   # old type of new label u
+    phi_p = [[phi[inv[u]][inv[v]] for v in range(3)] for u in range(3)]
+    rho_p = [rho[inv[u]] for u in range(3)]
+    emb_p = [emb[inv[u]] for u in range(3)]
+    box = configs.multi_box(5, 66, P.MULTI_MASS[:3], sigma_x=0.1)
+    a = oracle_lib.forces_at_multi(box.x, box.box, box.types, tabs3, RC, SKIN)
+    b = oracle_lib.forces_at_multi(box.x, box.box, np.asarray(perm)[box.types], (phi_p, rho_p, emb_p),
+                                   RC, SKIN)
+    for k in ("f", "rho", "fp"):
+        assert np.array_equal(a[k], b[k])
+    assert a["pe"] == b["pe"]
+
+
+def test_three_type_forces_are_minus_gradient(oracle_lib, tabs3):
+    box = configs.multi_box(4, 67, P.MULTI_MASS[:3], sigma_x=0.12)
+    res = oracle_lib.forces_at_multi(box.x, box.box, box.types, tabs3, RC, SKIN)
+    h = 1e-4
+    for t in range(3):
+        i = int(np.nonzero(box.types == t)[0][0])
+        for d in range(3):
+            xp, xm = box.x.copy(), box.x.copy()
+            xp[i, d] += h
+            xm[i, d] -= h
+            ep = oracle_lib.forces_at_multi(xp, box.box, box.types, tabs3, RC, SKIN)["pe"]
+            em = oracle_lib.forces_at_multi(xm, box.box, box.types, tabs3, RC, SKIN)["pe"]
+            assert abs(-(ep - em) / (2 * h) - res["f"][i, d]) < 1e-7

@@ -221,6 +221,21 @@ def alloy_box(n_cells: int, seed: int, *, frac_1: float = 0.5, masses=(180.95, 9
                site_ids=np.arange(x.shape[0], dtype=np.int64), types=types)
 
 
+def multi_box(n_cells: int, seed: int, masses, *, sigma_x: float = 0.05,
+              temperature: float = 300.0, a: float = A_LAT) -> Box:
+    """BCC box whose sites hold types drawn uniformly from range(len(masses)).
+    Draw order: displacements, types, velocities."""
+    rng = np.random.default_rng(seed)
+    sites = bcc_sites(n_cells, a)
+    x = sites + sigma_x * rng.standard_normal(sites.shape)
+    box = np.full(3, n_cells * a)
+    x = wrap_into_box(x, box)
+    types = rng.integers(0, len(masses), x.shape[0]).astype(np.int32)
+    v = maxwell_boltzmann_masses(rng, np.asarray(masses)[types], temperature)
+    return Box(x=x, v=v, box=box, n_cells=n_cells, temperature=temperature,
+               site_ids=np.arange(x.shape[0], dtype=np.int64), types=types)
+
+
 def config_alloy_128k() -> Box:
     """128,000-atom random equiatomic binary BCC alloy (40^3 cells), 300 K, seed 7."""
     return alloy_box(40, 7)

@@ -220,10 +220,16 @@ ALLOY_R0 = (R0, 2.72)
 ALLOY_RHO_S = (1.0, 0.8)
 ALLOY_EMB_A = (EMB_A, 2.4)
 ALLOY_MASS = (180.95, 95.95)
+# two more synthetic species of the same forms, for three- and four-type systems
+# (types 0 and 1 are the binary alloy's)
+MULTI_R0 = ALLOY_R0 + (2.80, 2.66)
+MULTI_RHO_S = ALLOY_RHO_S + (0.9, 1.15)
+MULTI_EMB_A = ALLOY_EMB_A + (2.7, 2.2)
+MULTI_MASS = ALLOY_MASS + (63.55, 55.85)
 
 
 def alloy_r0(a: int, b: int) -> float:
-    return 0.5 * (ALLOY_R0[a] + ALLOY_R0[b])
+    return 0.5 * (MULTI_R0[a] + MULTI_R0[b])
 
 
 def alloy_phi(r, a, b):
@@ -239,27 +245,29 @@ def alloy_dphi(r, a, b):
 
 def alloy_rho(r, t):
     r = np.asarray(r, dtype=np.float64)
-    return ALLOY_RHO_S[t] * np.exp(-RHO_B * (r / ALLOY_R0[t] - 1.0)) * fc(r)
+    return MULTI_RHO_S[t] * np.exp(-RHO_B * (r / MULTI_R0[t] - 1.0)) * fc(r)
 
 
 def alloy_drho(r, t):
     r = np.asarray(r, dtype=np.float64)
-    e = ALLOY_RHO_S[t] * np.exp(-RHO_B * (r / ALLOY_R0[t] - 1.0))
-    return e * (-RHO_B / ALLOY_R0[t]) * fc(r) + e * dfc(r)
+    e = MULTI_RHO_S[t] * np.exp(-RHO_B * (r / MULTI_R0[t] - 1.0))
+    return e * (-RHO_B / MULTI_R0[t]) * fc(r) + e * dfc(r)
 
 
 def alloy_emb(x, t):
-    return -ALLOY_EMB_A[t] * np.sqrt(np.asarray(x, dtype=np.float64))
+    return -MULTI_EMB_A[t] * np.sqrt(np.asarray(x, dtype=np.float64))
 
 
 def alloy_demb(x, t):
-    return -0.5 * ALLOY_EMB_A[t] / np.sqrt(np.asarray(x, dtype=np.float64))
+    return -0.5 * MULTI_EMB_A[t] / np.sqrt(np.asarray(x, dtype=np.float64))
 
 
-def alloy_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX):
-    """(phi[a][b], rho[t], F[t]) tables of the binary alloy: phi, rho on [0, rc],
-    F on [0, rho_max]; phi[a][b] and phi[b][a] are the same table."""
-    nt = len(ALLOY_R0)
+def alloy_tables(n_knots: int = N_KNOTS_MD, rho_max: float = RHO_MAX, n_types: int = 2):
+    """(phi[a][b], rho[t], F[t]) tables of the first n_types species (2: the
+    binary alloy): phi, rho on [0, rc], F on [0, rho_max]; phi[a][b] and
+    phi[b][a] are the same table."""
+    nt = n_types
+    assert 2 <= nt <= len(MULTI_R0)
     phi_t = [[None] * nt for _ in range(nt)]
     for a in range(nt):
         for b in range(a, nt):
