@@ -56,13 +56,14 @@ def test_loss_forces_gradient_match_oracle(fm, oracle_lib, n_cfg, ncell):
     prob.close()
 
 
-def test_orthorhombic_configurations(fm, oracle_lib):
-    """Configurations with three different periodic edge lengths (the adjoint
-    kernels apply image shifts of their own)."""
+def test_orthorhombic_and_open_configurations(fm, oracle_lib):
+    """Configurations with three different periodic edge lengths, and a slab
+    open in x and y (the adjoint kernels apply image shifts of their own)."""
     import torch
 
     boxes = [configs.ortho_box(5, 6, 7, seed=120, sigma_x=0.1, temperature=0.0),
-             configs.ortho_box(7, 5, 6, seed=121, sigma_x=0.1, temperature=0.0)]
+             configs.ortho_box(7, 5, 6, seed=121, sigma_x=0.1, temperature=0.0),
+             configs.slab(6, 6, 5, seed=122, sigma_x=0.1, vacuum=3.0, temperature=0.0)]
     x, off, bx, fref = _problem(oracle_lib, boxes)
     tabs = P.fm_tables()
     _say(f"[gpu] force matching orthorhombic n={x.shape[0]}")

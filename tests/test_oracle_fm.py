@@ -159,3 +159,28 @@ def test_orthorhombic_configurations_by_central_difference(oracle_lib):
         lp = _loss(oracle_lib, pb, _with(pb["tabs"], 0, q, h))
         lm = _loss(oracle_lib, pb, _with(pb["tabs"], 0, q, -h))
         assert abs((lp - lm) / (2 * h) - g[q]) <= tol
+
+
+def test_open_slab_configuration_by_central_difference(oracle_lib):
+    """A configuration with open x and y (a slab) next to a periodic one: the
+    phi gradient against central differences."""
+    boxes = [configs.slab(6, 6, 5, seed=112, sigma_x=0.12, vacuum=3.0, temperature=0.0),
+             configs.small_box(5, seed=113, sigma_x=0.12, temperature=0.0)]
+    x = np.concatenate([b.x for b in boxes])
+    off = np.array([0, boxes[0].n, boxes[0].n + boxes[1].n], np.int64)
+    bx = np.stack([b.box for b in boxes])
+    assert bx[0, 0] < 0 and bx[0, 1] < 0
+    fref = np.concatenate([oracle_lib.forces_analytic(b.x, b.box, P.analytic_params())[0]
+                           for b in boxes])
+    pb = dict(x=x, off=off, boxes=bx, fref=fref, tabs=P.fm_tables())
+    _, grads, _ = oracle_lib.fm_loss_grad(x, off, bx, pb["tabs"], fref)
+    g = grads[0].ravel()
+    nz = np.nonzero(g)[0]
+    pick = nz[np.argsort(-np.abs(g[nz]))[:8]]
+    h = 1e-6
+    loss0 = _loss(oracle_lib, pb, pb["tabs"])
+    tol = 8 * np.finfo(float).eps * loss0 / h
+    for q in pick:
+        lp = _loss(oracle_lib, pb, _with(pb["tabs"], 0, q, h))
+        lm = _loss(oracle_lib, pb, _with(pb["tabs"], 0, q, -h))
+        assert abs((lp - lm) / (2 * h) - g[q]) <= tol
