@@ -71,6 +71,7 @@ CASES = [
     ("min_3cells", lambda: configs.small_box(5, seed=32, sigma_x=0.2, temperature=300.0)),
     ("hot_12cells", lambda: configs.small_box(12, seed=33, sigma_x=0.25, temperature=2500.0)),
     ("slab_open", lambda: configs.slab(7, 9, 6, seed=32, sigma_x=0.2, vacuum=6.0)),
+    ("ortho_5x6x7", lambda: configs.ortho_box(5, 6, 7, seed=38, sigma_x=0.1, temperature=900.0)),
 ]
 
 

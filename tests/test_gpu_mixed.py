@@ -26,6 +26,7 @@ MIXED_CASES = [
     ("box_8cells_2500K", lambda: configs.small_box(8, seed=62, temperature=2500.0,
                                                    sigma_x=0.02 * np.sqrt(2500.0 / 300))),
     ("slab_open_xy", lambda: configs.slab(7, 7, 5, seed=63, sigma_x=0.05, vacuum=6.0)),
+    ("ortho_5x6x7", lambda: configs.ortho_box(5, 6, 7, seed=64, sigma_x=0.05)),
 ]
 
 
