@@ -3,7 +3,7 @@
 // coefficients of phi, rho and F.
 //
 // Forces follow Eq. (EAMforce) of the paper (arXiv 2405.07898, Sec. II-A),
-// with rho, F and phi the "arbitrary polynomial splines" it allows.  The
+// with rho, F and phi polynomial splines of any coefficients, as the paper allows.  The
 // gradient is reverse-mode differentiation of the density and force passes:
 //   g_i = 2 (F_i - Fref_i),  u_ij = (x_j - x_i)/r,  w_ij = g_i . u_ij
 //   lambda_i = sum_j (g_i - g_j) . u_ij rho'(r_ij),  mu_i = lambda_i F''(rho_i)
