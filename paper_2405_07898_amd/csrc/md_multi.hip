@@ -147,6 +147,13 @@ __device__ __forceinline__ void fill_force_rows(double* lds, const MultiTables& 
   }
 }
 
+// A read of the force rows in the LDS through an LDS-typed pointer: the
+// compiler then cannot fold it with the global-memory fallback below into one
+// generic (flat) load, which would wait on global memory as well.
+__device__ __forceinline__ double lds_ld(const double* p) {
+  return *(const __attribute__((address_space(3))) double*)p;
+}
+
 template <int LPA>
 __device__ __forceinline__ void pair_forces_multi(const Geometry& g, const State& s,
                                                   const MultiTables& t, const double* lds_rows,
@@ -192,8 +199,9 @@ __device__ __forceinline__ void pair_forces_multi(const Geometry& g, const State
       // or (a pair closer than the LDS segments, rare) from global memory
       const int oj = 3 * tj[u], oi = 3 * ti, op = 3 * t.pair_row[ti * T + tj[u]];
       const double* seg = lds_rows + max(kk - t.lds_seg0, 0) * lw;
-      double c[9] = {seg[oj], seg[oj + 1], seg[oj + 2], seg[oi], seg[oi + 1],
-                     seg[oi + 2], seg[op], seg[op + 1], seg[op + 2]};
+      double c[9] = {lds_ld(seg + oj), lds_ld(seg + oj + 1), lds_ld(seg + oj + 2),
+                     lds_ld(seg + oi), lds_ld(seg + oi + 1), lds_ld(seg + oi + 2),
+                     lds_ld(seg + op), lds_ld(seg + op + 1), lds_ld(seg + op + 2)};
       if (kk < t.lds_seg0) {
         const double* gs = t.frow + (size_t)kk * t.seg_stride;
         c[0] = gs[oj]; c[1] = gs[oj + 1]; c[2] = gs[oj + 2];
