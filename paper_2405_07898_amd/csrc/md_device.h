@@ -1,5 +1,5 @@
 // md_device.h -- device helpers shared by the kernel sources of the MI355X
-// EAM library (md_kernels.hip, md_half.hip).
+// EAM library (md_kernels.hip, md_half.hip, md_multi.hip, md_fm.hip).
 #pragma once
 
 #include <math.h>

@@ -27,6 +27,7 @@
 
 #include "md.h"
 #include "md_internal.h"
+#include "md_device.h"
 
 #pragma clang fp contract(off)
 
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(64) void k_fm_density(FmArgs a) {
       double dx, dy, dz;
       sep(rp, e[u], pi, pj[u], dx, dy, dz);
       const double r2 = (dx * dx + dy * dy) + dz * dz;
-      if (r2 < a.rc2) acc += sp_f(a.rho, sqrt(r2));
+      if (r2 < a.rc2) acc += sp_f(a.rho, r2 * rsq64(r2));
     }
   }
   a.rho_i[i] = acc;
@@ -182,11 +183,13 @@ __global__ __launch_bounds__(64) void k_fm_force(FmArgs a) {
         sep(rp, e[u], pi, pj[u], dx, dy, dz);
         const double r2 = (dx * dx + dy * dy) + dz * dz;
         if (r2 < a.rc2) {
-          const double r = sqrt(r2);
+          // r^-1 as in the MD passes: no division, no square root
+          const double rinv = rsq64(r2);
+          const double r = r2 * rinv;
           const double sc = (fpi + fpj[u]) * sp_df(a.rho, r) + sp_df(a.phi, r);
-          fx += sc * dx / r;
-          fy += sc * dy / r;
-          fz += sc * dz / r;
+          fx += sc * dx * rinv;
+          fy += sc * dy * rinv;
+          fz += sc * dz * rinv;
         }
       }
     }
@@ -254,9 +257,10 @@ __global__ __launch_bounds__(64) void k_fm_lambda(FmArgs a) {
         sep(rp, e[u], pi, pj[u], dx, dy, dz);
         const double r2 = (dx * dx + dy * dy) + dz * dz;
         if (r2 < a.rc2) {
-          const double r = sqrt(r2);
+          const double rinv = rsq64(r2);
+          const double r = r2 * rinv;
           const double sij =
-              ((gi.x - gj[u].x) * dx + (gi.y - gj[u].y) * dy + (gi.z - gj[u].z) * dz) / r;
+              ((gi.x - gj[u].x) * dx + (gi.y - gj[u].y) * dy + (gi.z - gj[u].z) * dz) * rinv;
           acc += sij * sp_df(a.rho, r);
           fpmax = fmax(fpmax, fabs(fpj[u]));
         }
@@ -357,8 +361,9 @@ __global__ __launch_bounds__(64) void k_fm_coef(FmArgs a) {
         sep(rp, e[u], pi, pj[u], dx, dy, dz);
         const double r2 = (dx * dx + dy * dy) + dz * dz;
         if (!(r2 < a.rc2)) continue;
-        const double r = sqrt(r2);
-        const double w = (gi.x * dx + gi.y * dy + gi.z * dz) / r;
+        const double rinv = rsq64(r2);
+        const double r = r2 * rinv;
+        const double w = (gi.x * dx + gi.y * dy + gi.z * dz) * rinv;
         int kp;
         double tp;
         seg(a.phi, r, kp, tp);
