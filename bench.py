@@ -208,25 +208,6 @@ def bench_small(torch, md, configs, tabs):
             "persistent_launch_timesteps_per_s": round(2000 / sec_p, 1)}
 
 
-def bench_stable(torch, md, configs, potential, steps):
-    """Context only, not the specified workload: the 128,000-atom box with the
-    STABLE parameter set (a solid at 300 K, rebuilds about every 50 steps)."""
-    box = configs.config_128k()
-    tabs = potential.md_tables(p=potential.STABLE)
-    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
-    lpa, _ = s.autotune(50)
-    s.step(100)
-    st0 = s.stats()
-    sec, _ = time_steps(torch, s, steps)
-    st1 = s.stats()
-    s.close()
-    return {"potential": "STABLE (context only; not the benchmark's potential)",
-            "n_atoms": box.n, "steps": steps, "lanes_per_atom": lpa,
-            "timesteps_per_s": round(steps / sec, 1),
-            "rebuilds": int(st1["rebuilds"] - st0["rebuilds"]),
-            "mean_list_length": round(st1["list_entries"] / box.n, 3)}
-
-
 def bench_slab(torch, md, configs, tabs, steps):
     """The paper's benchmark geometry (Sec. IV-B): an 801,792-atom BCC slab of
     256 x 261 x 6 cells, open in x and y, periodic through its thickness, at
@@ -589,8 +570,6 @@ def main() -> int:
         log(f"  half list: {out['secondary_half_list_128k']}")
         out["secondary_alloy_128k"] = bench_alloy(torch, md, configs, potential, 5000)
         log(f"  binary alloy: {out['secondary_alloy_128k']}")
-        out["secondary_stable_128k"] = bench_stable(torch, md, configs, potential, 5000)
-        log(f"  stable-lattice context: {out['secondary_stable_128k']}")
         out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)
         out["secondary_perf_model"] = perf_model(torch, md, configs, tabs)
         pm = out["secondary_perf_model"]

@@ -47,8 +47,7 @@ class MDStats(C.Structure):
 
 class Analytic(C.Structure):
     _fields_ = [("rc", C.c_double), ("r0", C.c_double), ("phi_a", C.c_double),
-                ("phi_b", C.c_double), ("rho_b", C.c_double), ("emb_a", C.c_double),
-                ("well_w", C.c_double), ("well_s", C.c_double), ("well_r", C.c_double)]
+                ("phi_b", C.c_double), ("rho_b", C.c_double), ("emb_a", C.c_double)]
 
 
 _lib = None
@@ -246,12 +245,11 @@ def forces_at(x, box, tables, rc, skin=0.0, cap=256):
 
 def forces_analytic(x, box, params):
     """Forces and energy of the closed-form potential; params holds rc, r0, phi_a,
-    phi_b, rho_b, emb_a, well_w, well_s, well_r (the synthetic potential's constants)."""
+    phi_b, rho_b, emb_a (the synthetic potential's constants)."""
     x = _f64(x)
     f = np.empty_like(x)
     pe = C.c_double()
-    an = Analytic(*[float(params[k]) for k in ("rc", "r0", "phi_a", "phi_b", "rho_b", "emb_a",
-                                                "well_w", "well_s", "well_r")])
+    an = Analytic(*[float(params[k]) for k in ("rc", "r0", "phi_a", "phi_b", "rho_b", "emb_a")])
     code = lib().or_forces_analytic(x.shape[0], _pd(x), _pd(_f64(box)), C.byref(an), _pd(f),
                                     C.byref(pe))
     if code != OR_OK:

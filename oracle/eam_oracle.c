@@ -557,11 +557,10 @@ int32_t or_forces_at(int64_t n, const double *x_in, const double box[3], double 
 /* ------------------------------------------------------- analytic potential */
 
 /* Closed-form synthetic potential: fc = (1-(r/rc)^2)^3,
- * phi = (A e^{-B(r/r0-1)} - W e^{-((r-rw)/s)^2}) fc, rho = e^{-C(r/r0-1)} fc,
- * F = -E sqrt(rho).  Used for force-matching reference forces and to pin the
- * tabulated path. */
+ * phi = A e^{-B(r/r0-1)} fc, rho = e^{-C(r/r0-1)} fc, F = -E sqrt(rho).
+ * Used for force-matching reference forces and to pin the tabulated path. */
 typedef struct {
-  double rc, r0, phi_a, phi_b, rho_b, emb_a, well_w, well_s, well_r;
+  double rc, r0, phi_a, phi_b, rho_b, emb_a;
 } or_analytic;
 
 static void an_pair(const or_analytic *a, double r, double *ph, double *dph, double *rh,
@@ -571,12 +570,8 @@ static void an_pair(const or_analytic *a, double r, double *ph, double *dph, dou
   double df = 3.0 * u * u * (-2.0 * r / (a->rc * a->rc));
   double ep = a->phi_a * exp(-a->phi_b * (r / a->r0 - 1.0));
   double er = exp(-a->rho_b * (r / a->r0 - 1.0));
-  double w = (r - a->well_r) / a->well_s;
-  double ew = a->well_w * exp(-w * w);
-  double core = ep - ew;
-  double dcore = ep * (-a->phi_b / a->r0) + ew * (2.0 * w / a->well_s);
-  *ph = core * f;
-  *dph = dcore * f + core * df;
+  *ph = ep * f;
+  *dph = ep * (-a->phi_b / a->r0) * f + ep * df;
   *rh = er * f;
   *drh = er * (-a->rho_b / a->r0) * f + er * df;
 }

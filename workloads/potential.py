@@ -14,11 +14,6 @@ with rc = 5.0 and r0 = 2.86.  This BCC lattice at a = 3.304 is far from zero
 pressure and unstable under tetragonal shear, so MD boxes collapse and heat
 (hot, dense, frequent list rebuilds).
 
-STABLE is a second parameter set, used only for a labelled extra benchmark
-point: phi gets amplitude 1.5514 (zero pressure at a = 3.304) plus a shallow
-well -0.14 exp(-((r - 3.304)/0.2)^2) at the second-neighbour distance (positive
-shear modulus), and F = -3 sqrt(rho); its crystal stays solid at 300 K.
-
 Table layout (shared convention of both consumers): a spline with n knots on
 [x0, x0 + (n-1)*dx] stores, for every segment k in [0, n-2], four coefficients
 c0..c3 of the cubic in the normalised local coordinate t = (x - x0)/dx - k,
@@ -36,9 +31,6 @@ RC = 5.0
 R0 = 2.86
 PHI_A = 0.3
 PHI_B = 8.0
-WELL_W = 0.0
-WELL_S = 0.2
-WELL_R = 3.304
 RHO_B = 6.0
 EMB_A = 2.0
 RHO_MAX = 40.0
@@ -66,14 +58,12 @@ class SplineTable:
         return self.x0 + (self.n_knots - 1) * self.dx
 
 
-SPECIFIED = dict(phi_a=PHI_A, well_w=WELL_W, emb_a=EMB_A)
-STABLE = dict(phi_a=1.5514, well_w=0.14, emb_a=3.0)
+SPECIFIED = dict(phi_a=PHI_A, emb_a=EMB_A)
 
 
 def analytic_params(p: dict = SPECIFIED) -> dict:
     """All constants of a parameter set, for evaluators of the closed forms."""
-    return dict(rc=RC, r0=R0, phi_a=p["phi_a"], phi_b=PHI_B, rho_b=RHO_B, emb_a=p["emb_a"],
-                well_w=p["well_w"], well_s=WELL_S, well_r=WELL_R)
+    return dict(rc=RC, r0=R0, phi_a=p["phi_a"], phi_b=PHI_B, rho_b=RHO_B, emb_a=p["emb_a"])
 
 
 # --- analytic functions (vectorised numpy) ---------------------------------
@@ -92,15 +82,12 @@ def dfc(r):
 
 def _pair_core(r, p):
     r = np.asarray(r, dtype=np.float64)
-    return (p["phi_a"] * np.exp(-PHI_B * (r / R0 - 1.0))
-            - p["well_w"] * np.exp(-((r - WELL_R) / WELL_S) ** 2))
+    return p["phi_a"] * np.exp(-PHI_B * (r / R0 - 1.0))
 
 
 def _dpair_core(r, p):
     r = np.asarray(r, dtype=np.float64)
-    u = (r - WELL_R) / WELL_S
-    return (p["phi_a"] * (-PHI_B / R0) * np.exp(-PHI_B * (r / R0 - 1.0))
-            + p["well_w"] * (2.0 * u / WELL_S) * np.exp(-u ** 2))
+    return p["phi_a"] * (-PHI_B / R0) * np.exp(-PHI_B * (r / R0 - 1.0))
 
 
 def phi(r, p=SPECIFIED):
