@@ -57,7 +57,8 @@ typedef int32_t md_status;
 #define MD_E_LOST_ATOM (-9)     /* an atom moved more than one box length past a periodic edge */
 #define MD_E_WORKSPACE (-10)    /* workspace too small or misaligned */
 #define MD_E_STALL (-11)        /* a grid barrier of a persistent launch timed out */
-#define MD_W_RHO_RANGE 1        /* some rho_i exceeded the F table; last cubic extrapolated */
+#define MD_W_RHO_RANGE 1        /* some rho_i exceeded the F table's last knot; F continued
+                                   along its end tangent there */
 
 /* Precision of the pair passes. */
 #define MD_FP64 0  /* everything in float64 */
@@ -95,9 +96,11 @@ typedef int32_t md_status;
 /* A cubic spline on equally spaced knots x0 + k/inv_dx, k = 0..n_knots-1.
  * coef (host) holds (n_knots-1) rows of 4 float64: segment k evaluates
  * c0 + c1 t + c2 t^2 + c3 t^3 with t = (s - x0) inv_dx - k in [0,1); the
- * segment index is int((s - x0) inv_dx) clamped to [0, n_knots-2], so values
- * past the last knot extrapolate the last cubic (segment arithmetic as in the
- * paper's Table "flopmodel": x = alpha r, k = int(x), dx = x - k). */
+ * segment index is int((s - x0) inv_dx) clamped to [0, n_knots-2] (segment
+ * arithmetic as in the paper's Table "flopmodel": x = alpha r, k = int(x),
+ * dx = x - k).  Past the last knot a table continues along its end tangent:
+ * value f(end) + f'(end) (s - s_end), slope f'(end).  The r tables end at or
+ * past r_cut, so only the embedding F(rho) is ever evaluated there. */
 typedef struct md_spline {
   int32_t n_knots;
   int32_t reserved;
@@ -106,7 +109,13 @@ typedef struct md_spline {
   const double* coef;
 } md_spline;
 
-/* Parameters shared by all replicas of a context. */
+/* Parameters shared by all replicas of a context.  The per-box quantities
+ * (atom count, edge lengths, which dimensions are periodic) are not fields
+ * here: they are passed per replica (rep_atoms, rep_box) to md_init,
+ * md_init_batch, md_create and the workspace queries, a negative edge length
+ * marking an open dimension.  The rebuild rule is fixed: the list is rebuilt
+ * in the step after any atom of a replica moved more than skin/2 from its
+ * position at the last build. */
 typedef struct md_params {
   double mass;           /* amu */
   double dt;             /* fs */
@@ -159,6 +168,34 @@ typedef struct md_stats_t {
 md_status md_workspace_size(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
                             const double* rep_box, size_t* bytes);
 
+/* Same as md_workspace_size, returning the byte count (0 for invalid
+ * parameters or sizes). */
+size_t md_workspace_bytes(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                          const double* rep_box);
+
+/* Create a context for one box and upload its state in one call (md_create
+ * followed by md_set_state; the paper's per-atom state is identity, position
+ * and velocity, Sec. III-A, and set-up stays outside the timed MD loop,
+ * Sec. IV-B).  box: 3 edge lengths (host; negative = open dimension).
+ * x, v: device [n_atoms][3] float64, original order, on-step velocities.
+ * workspace: device, at least md_workspace_bytes(p, 1, &n_atoms, box) bytes,
+ * 256-byte aligned, borrowed until md_destroy.  On an error nothing is
+ * created (*out = NULL).  md_build_neighbors must follow before md_step. */
+md_status md_init(md_ctx** out, const md_params* p, int64_t n_atoms, const double* box,
+                  const md_spline* phi, const md_spline* rho, const md_spline* emb,
+                  const double* x, const double* v, void* workspace, size_t workspace_bytes,
+                  void* stream);
+
+/* md_init for n_rep independent boxes in one context (the batched form):
+ * replica r holds rep_atoms[r] atoms in box rep_box[3r..3r+2]; x and v hold
+ * all replicas concatenated in replica order.  Every pass runs all replicas
+ * in one launch; each replica rebuilds its list on its own schedule. */
+md_status md_init_batch(md_ctx** out, const md_params* p, int32_t n_rep,
+                        const int64_t* rep_atoms, const double* rep_box, const md_spline* phi,
+                        const md_spline* rho, const md_spline* emb, const double* x,
+                        const double* v, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
 /* Create a context.  phi(r), rho(r) tables must cover [0, r_cut]; emb(rho)
  * any range (values past its last knot raise MD_W_RHO_RANGE).  workspace is
  * a device pointer of at least md_workspace_size() bytes; stream is a
@@ -208,10 +245,13 @@ md_status md_build_neighbors(md_ctx* ctx);
 /* Advance n steps.  Each step: density pass, force pass fused with the
  * leap-frog kick and drift and the skin/2 displacement check; the list is
  * rebuilt on the device in the step after any atom moved more than skin/2.
- * Whole chunks run as one captured hipGraph.  On an error the state rolls
- * back to the start of the chunk in which it occurred (the status is
- * returned; md_stats().steps tells where).  n = 0 takes no step and returns
- * the latched status; n < 0 is MD_E_ARG. */
+ * Whole chunks run as one captured hipGraph; the steps left over (fewer than
+ * chunk_steps) run as one shorter captured graph, kept for reuse (a few
+ * lengths at a time).  With MD_LAUNCH_PERSISTENT the left-over steps are
+ * launched kernel by kernel.  On an error the state rolls back to the start
+ * of the graph (or chunk) in which it occurred (the status is returned;
+ * md_stats().steps tells where).  n = 0 takes no step and returns the latched
+ * status; n < 0 is MD_E_ARG. */
 md_status md_step(md_ctx* ctx, int64_t n);
 
 /* Potential and kinetic energy per replica (host arrays of n_rep doubles;
@@ -247,7 +287,7 @@ md_status md_launch_pass(md_ctx* ctx, int32_t pass, int32_t reps);
 
 /* Pair-pass schedule: lanes per atom (1, 2, 4 or 8) cooperating on one
  * atom's neighbour list, with a fixed-order shuffle reduction.  Results are
- * identical up to that reduction order.  Drops the captured step graph. */
+ * identical up to that reduction order.  Drops the captured step graphs. */
 md_status md_set_schedule(md_ctx* ctx, int32_t lanes_per_atom);
 
 /* Autotuner: times reps rounds of the step's density and force-plus-update

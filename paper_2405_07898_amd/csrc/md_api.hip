@@ -130,7 +130,15 @@ struct md_ctx {
   bool built = false;
   bool v_half = false;  // velocities are half-step (after build)
   int64_t chunks_since_sort = 0;
-  hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph = nullptr;  // chunk_steps steps from position buffer 0
+  // shorter graphs (len steps from position buffer `parity`) for the steps of
+  // an md_step call that do not fill a chunk; a few are kept
+  struct Tail {
+    int32_t len;
+    int32_t parity;
+    hipGraphExec_t exec;
+  };
+  std::vector<Tail> tails;
   int persist_cap = 0;  // most co-resident workgroups of the persistent kernel
   std::string err;
 };
@@ -425,13 +433,15 @@ md_status step_eager(md_ctx* c) {
   return MD_OK;
 }
 
-md_status capture_chunk(md_ctx* c) {
-  if (c->graph) return MD_OK;
+// Capture `len` steps starting from the current position buffer into one
+// executable graph (the context's buffer parity is left unchanged).
+md_status capture_steps(md_ctx* c, int len, hipGraphExec_t* out) {
+  *out = nullptr;
   hipGraph_t gr = nullptr;
   HIPC(c, hipStreamBeginCapture(c->L.stream, hipStreamCaptureModeRelaxed));
   const int saved = c->cur;
   md_status rc = MD_OK;
-  for (int k = 0; k < c->p.chunk_steps && rc == MD_OK; ++k) rc = step_eager(c);
+  for (int k = 0; k < len && rc == MD_OK; ++k) rc = step_eager(c);
   c->cur = saved;
   hipError_t e = hipStreamEndCapture(c->L.stream, &gr);
   if (rc != MD_OK) {
@@ -439,12 +449,49 @@ md_status capture_chunk(md_ctx* c) {
     return rc;
   }
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
   if (e != hipSuccess) {
-    c->graph = nullptr;
+    *out = nullptr;
     return hip_fail(c, e, "hipGraphInstantiate");
   }
+  return MD_OK;
+}
+
+md_status capture_chunk(md_ctx* c) {
+  if (c->graph) return MD_OK;
+  return capture_steps(c, c->p.chunk_steps, &c->graph);
+}
+
+constexpr size_t kMaxTailGraphs = 4;
+
+// The graph of `len` steps from the current buffer parity (captured on first use).
+md_status tail_graph(md_ctx* c, int len, hipGraphExec_t* out) {
+  for (const md_ctx::Tail& t : c->tails)
+    if (t.len == len && t.parity == c->cur) {
+      *out = t.exec;
+      return MD_OK;
+    }
+  if (c->tails.size() >= kMaxTailGraphs) {
+    // the oldest may still run on the stream
+    HIPC(c, hipStreamSynchronize(c->L.stream));
+    (void)hipGraphExecDestroy(c->tails.front().exec);
+    c->tails.erase(c->tails.begin());
+  }
+  md_status s = capture_steps(c, len, out);
+  if (s != MD_OK) return s;
+  c->tails.push_back(md_ctx::Tail{len, c->cur, *out});
+  return MD_OK;
+}
+
+// Drop every captured graph (the schedule they were captured with changed).
+md_status drop_graphs(md_ctx* c) {
+  if (!c->graph && c->tails.empty()) return MD_OK;
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  for (const md_ctx::Tail& t : c->tails) (void)hipGraphExecDestroy(t.exec);
+  c->tails.clear();
   return MD_OK;
 }
 
@@ -901,6 +948,42 @@ md_status md_create_multi(md_ctx** out, const md_params* p, int32_t n_rep,
                      workspace_bytes, stream);
 }
 
+size_t md_workspace_bytes(const md_params* p, int32_t n_rep, const int64_t* rep_atoms,
+                          const double* rep_box) {
+  size_t b = 0;
+  return md_workspace_size(p, n_rep, rep_atoms, rep_box, &b) == MD_OK ? b : 0;
+}
+
+md_status md_init_batch(md_ctx** out, const md_params* p, int32_t n_rep,
+                        const int64_t* rep_atoms, const double* rep_box, const md_spline* phi,
+                        const md_spline* rho, const md_spline* emb, const double* x,
+                        const double* v, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  if (!out) return MD_E_ARG;
+  *out = nullptr;
+  if (!x || !v) return MD_E_ARG;
+  md_ctx* c = nullptr;
+  md_status s = md_create(&c, p, n_rep, rep_atoms, rep_box, phi, rho, emb, workspace,
+                          workspace_bytes, stream);
+  if (s != MD_OK) return s;
+  s = md_set_state(c, x, v);
+  if (s < 0) {
+    g_last_error = c->err;
+    md_destroy(c);
+    return s;
+  }
+  *out = c;
+  return s;
+}
+
+md_status md_init(md_ctx** out, const md_params* p, int64_t n_atoms, const double* box,
+                  const md_spline* phi, const md_spline* rho, const md_spline* emb,
+                  const double* x, const double* v, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+  return md_init_batch(out, p, 1, &n_atoms, box, phi, rho, emb, x, v, workspace,
+                       workspace_bytes, stream);
+}
+
 md_status md_set_types(md_ctx* c, const int32_t* type) {
   if (!c || !type) return MD_E_ARG;
   if (!c->multi) return MD_E_ARG;
@@ -972,9 +1055,19 @@ md_status md_step(md_ctx* c, int64_t n) {
       }
       ++c->chunks_since_sort;
       done += chunk;
-    } else {
+    } else if (c->p.launch_mode == MD_LAUNCH_PERSISTENT) {
       if ((s = step_eager(c)) != MD_OK) return s;
       ++done;
+    } else {
+      // fewer steps than a chunk, or an odd buffer parity: one shorter graph
+      // (chunk_steps - 1 is odd, so a parity-1 start ends on buffer 0)
+      const int len = (int)std::min<int64_t>(n - done, chunk - 1);
+      hipGraphExec_t ge = nullptr;
+      if ((s = tail_graph(c, len, &ge)) != MD_OK) return s;
+      HIPC(c, launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, false));
+      HIPC(c, hipGraphLaunch(ge, c->L.stream));
+      if (len & 1) c->cur = 1 - c->cur;
+      done += len;
     }
   }
   int32_t w[SW_WORDS];
@@ -1139,10 +1232,9 @@ md_status md_set_schedule(md_ctx* c, int32_t lanes_per_atom) {
   if (!c) return MD_E_ARG;
   const int l = lanes_per_atom;
   if (!(l == 1 || l == 2 || l == 4 || l == 8)) return MD_E_ARG;
-  if (l != c->lpa && c->graph) {
-    HIPC(c, hipStreamSynchronize(c->L.stream));
-    (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
+  if (l != c->lpa) {
+    md_status s = drop_graphs(c);
+    if (s != MD_OK) return s;
   }
   c->lpa = l;
   return MD_OK;
@@ -1213,7 +1305,7 @@ md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us
 
 void md_destroy(md_ctx* c) {
   if (!c) return;
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  (void)drop_graphs(c);
   delete c;
 }
 

@@ -509,10 +509,13 @@ __global__ __launch_bounds__(1024) void k_scan_cells(const int32_t* __restrict__
 }
 
 // One thread per cell: order the cell's atoms by original id and gather
-// positions, velocities and ids into the sorted scratch arrays.
+// positions, velocities and ids into the sorted scratch arrays.  A binning
+// that overflowed a cell or lost an atom (error latched) places fewer than n
+// atoms: then neither this kernel nor the copy-back moves anything, and the
+// slot order stays as it was.
 __global__ __launch_bounds__(256) void k_sort_scatter(State s, int64_t m, int32_t cap) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= m) return;
+  if (c >= m || has_error(s.status)) return;
   const int32_t n = min(s.bin_cnt[c], cap);
   const int32_t* b = s.bin_idx + c * cap;
   const int32_t base = s.cell_start[c];
@@ -529,7 +532,9 @@ __global__ __launch_bounds__(256) void k_sort_scatter(State s, int64_t m, int32_
 }
 
 __global__ __launch_bounds__(256) void k_sort_copyback(State s, int64_t n, int64_t m) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+  // a failed binning (error latched, or fewer than n atoms placed) moves nothing
+  const bool moved = !has_error(s.status) && s.cell_start[m] == (int32_t)n;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; moved && k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
     s.pos[k] = s.sort_pos[k];
     s.vel[k] = s.sort_vel[k];

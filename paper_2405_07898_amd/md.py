@@ -56,7 +56,7 @@ class md_stats_t(C.Structure):
 _lib = None
 
 EXPORTED = [
-    "md_workspace_size", "md_create", "md_set_state", "md_build_neighbors", "md_step",
+    "md_workspace_size", "md_workspace_bytes", "md_init", "md_init_batch", "md_create", "md_set_state", "md_build_neighbors", "md_step",
     "md_energy", "md_get_state", "md_compute_forces", "md_stats", "md_get_cells",
     "md_get_neighbors", "md_launch_pass", "md_set_schedule", "md_autotune", "md_last_error",
     "md_status_string", "md_destroy", "md_create_multi", "md_set_types",
@@ -75,6 +75,11 @@ def lib():
         i32, i64, d, sz = C.c_int32, C.c_int64, C.c_double, C.c_size_t
         sig = {
             "md_workspace_size": (i32, [P(md_params), i32, P(i64), P(d), P(sz)]),
+            "md_workspace_bytes": (sz, [P(md_params), i32, P(i64), P(d)]),
+            "md_init": (i32, [P(vp), P(md_params), i64, P(d), P(md_spline), P(md_spline),
+                              P(md_spline), vp, vp, vp, sz, vp]),
+            "md_init_batch": (i32, [P(vp), P(md_params), i32, P(i64), P(d), P(md_spline),
+                                    P(md_spline), P(md_spline), vp, vp, vp, sz, vp]),
             "md_create": (i32, [P(vp), P(md_params), i32, P(i64), P(d), P(md_spline),
                                 P(md_spline), P(md_spline), vp, sz, vp]),
             "md_create_multi": (i32, [P(vp), P(md_params), i32, P(i64), P(d), P(md_spline),

@@ -13,13 +13,15 @@ LIB = os.path.join(ROOT, "paper_2405_07898_amd", "libmdeam.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:md_status|void|const char\*)\s+(md_\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:md_status|void|size_t|const char\*)\s+(md_\w+)\s*\(", text,
+                       flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_api():
     names = declared_functions()
-    for required in ("md_create", "md_build_neighbors", "md_step", "md_energy", "md_fm_forward",
+    for required in ("md_init", "md_init_batch", "md_workspace_bytes", "md_create",
+                     "md_build_neighbors", "md_step", "md_energy", "md_fm_forward",
                      "md_fm_backward", "md_autotune"):
         assert required in names
 
@@ -230,3 +232,48 @@ def test_no_replicas_without_gpu():
     rc = lib.md_workspace_size(ctypes.byref(p), 0, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.byref(out))
     assert rc == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+def test_workspace_bytes_matches_workspace_size_without_gpu():
+    """md_workspace_bytes returns md_workspace_size's count, and 0 for sizes
+    that md_workspace_size rejects."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0)
+    n = (ctypes.c_int64 * 2)(1000, 250)
+    b = np.array([[20.0, 20.0, 20.0], [-30.0, -30.0, 16.0]], dtype=np.float64)
+    bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    out = ctypes.c_size_t(0)
+    assert lib.md_workspace_size(ctypes.byref(p), 2, n, bp, ctypes.byref(out)) == 0
+    assert lib.md_workspace_bytes(ctypes.byref(p), 2, n, bp) == out.value > 0
+    bad = np.array([[10.0, 20.0, 20.0]], dtype=np.float64)
+    assert lib.md_workspace_bytes(ctypes.byref(p), 1, n,
+                                  bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    assert lib.md_workspace_bytes(None, 1, n, bp) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmdeam.so not built")
+def test_init_rejects_bad_arguments_without_gpu():
+    """md_init / md_init_batch validate parameters, sizes and the box on the
+    host before any device call, and leave *out NULL."""
+    import numpy as np
+
+    from paper_2405_07898_amd import md
+
+    lib = md.lib()
+    p = md.make_params(mass=183.84, dt=1.0, r_cut=5.0, skin=0.3, ftm2v=1.0)
+    ctx = ctypes.c_void_p(1234)
+    box = np.array([10.0, 20.0, 20.0])  # below 2 (r_cut + skin)
+    rc = lib.md_init(ctypes.byref(ctx), ctypes.byref(p), 100,
+                     box.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, None,
+                     ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20,
+                     None)
+    assert rc in (md.MD_E_BOX, md.MD_E_TABLE) and ctx.value is None
+    ctx = ctypes.c_void_p(1234)
+    rc = lib.md_init_batch(ctypes.byref(ctx), ctypes.byref(p), 1, None, None, None, None, None,
+                           None, None, None, 0, None)
+    assert rc == md.MD_E_ARG and ctx.value is None

@@ -5,6 +5,7 @@ import sys
 import numpy as np
 import pytest
 
+from mixed_bound import pair_bounds
 from workloads import configs, potential as P
 
 pytestmark = pytest.mark.gpu
@@ -67,3 +68,40 @@ def test_batch_equals_alone_and_oracle(oracle_lib, lpa):
         d = xa - out["x"]
         d -= b.box * np.round(d / b.box)
         assert np.max(np.abs(d)) < 1e-9, (r, np.max(np.abs(d)))
+
+
+@pytest.mark.parametrize("lpa", [1, 4])
+def test_batch_mixed_equals_alone_and_within_float32_bound(oracle_lib, lpa):
+    """Mixed precision in a batch: each replica's forces bitwise equal to the
+    replica alone, and every rho_i and force of every replica within the
+    float32 bound (mixed_bound.py) of the float64 oracle."""
+    import torch
+
+    from paper_2405_07898_amd import md
+
+    assert torch.cuda.is_available()
+    tabs = P.md_tables()
+    reps = _replicas(5)
+    _say(f"[gpu] mixed batch of {len(reps)} replicas sizes {[b.n for b in reps]} lpa={lpa}")
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V,
+                       chunk_steps=20, lanes_per_atom=lpa, precision=md.MD_MIXED)
+    batch = md.System(p, tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
+    batch.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
+    batch.build_neighbors()
+    fb, rb, _ = (t.cpu().numpy() for t in batch.compute_forces())
+    batch.close()
+    off = np.concatenate([[0], np.cumsum([b.n for b in reps])])
+    for r, b in enumerate(reps):
+        alone = md.System(p, tabs, [b.n], b.box[None, :])
+        alone.set_state(b.x, b.v)
+        alone.build_neighbors()
+        fa, ra, _ = (t.cpu().numpy() for t in alone.compute_forces())
+        alone.close()
+        sl = slice(off[r], off[r + 1])
+        assert np.array_equal(fb[sl], fa) and np.array_equal(rb[sl], ra), r
+        ref = oracle_lib.forces_at(b.x, b.box, tabs, RC, SKIN)
+        cnt, nbr, _ = oracle_lib.neighbor_list(b.x, b.box, RC + SKIN, cap=128)
+        rho_bound, f_bound = pair_bounds(b.x, b.box, ref["fp"], cnt, nbr)
+        assert np.all(np.abs(rb[sl] - ref["rho"]) <= rho_bound), r
+        err = np.linalg.norm(fb[sl] - ref["f"], axis=1)
+        assert np.all(err <= f_bound), (r, float(np.max(err / f_bound)))

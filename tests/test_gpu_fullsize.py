@@ -4,8 +4,8 @@ The 128,000-atom and 802,344-atom periodic boxes and the 801,792-atom slab
 (open in x and y) are built with the same parameters as
 bench.py (hipGraph chunks of 100 steps, list capacity 128, cell capacity 64,
 lanes per atom from the autotuner).  Against the FP64 oracle:
-- cell ids of every atom and list lengths of every atom: bit-exact;
-- neighbour sets: bit-exact on a seeded sample of 4,096 atoms;
+- cell ids, list lengths and neighbour sets of every atom: bit-exact (each
+  atom's set compared as its sorted row);
 - rho_i, F'(rho_i): 1e-12 relative; forces: 1e-10 relative (max-norm over
   atoms, relative to the largest force); potential energy: 1e-12 relative;
 - after 100 graph-captured steps: positions within 1e-9 A, velocities within
@@ -28,6 +28,12 @@ RC, SKIN = P.RC, configs.SKIN
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def _sorted_rows(nbr, cnt):
+    """Each atom's neighbour set as its sorted row (unused slots last)."""
+    valid = np.arange(nbr.shape[1])[None, :] < cnt[:, None]
+    return np.sort(np.where(valid, nbr, np.iinfo(np.int32).max), axis=1)
 
 
 def _rel(a, b):
@@ -68,9 +74,7 @@ def test_full_size_cells_lists_forces(md, tabs, oracle_lib, name, make):
     cnt_g, nbr_g = cnt_g.cpu().numpy(), nbr_g.cpu().numpy()
     cnt_o, nbr_o, _ = oracle_lib.neighbor_list(box.x, box.box, RC + SKIN, cap=128)
     assert np.array_equal(cnt_g, cnt_o)
-    pick = np.sort(np.random.default_rng(7).choice(box.n, 4096, replace=False))
-    for i in pick:
-        assert set(nbr_g[i, :cnt_g[i]].tolist()) == set(nbr_o[i, :cnt_o[i]].tolist()), i
+    assert np.array_equal(_sorted_rows(nbr_g, cnt_g), _sorted_rows(nbr_o, cnt_o))
     f, rho, fp = s.compute_forces()
     ref = oracle_lib.forces_at(box.x, box.box, tabs, RC, SKIN)
     assert _rel(rho.cpu().numpy(), ref["rho"]) < 1e-12
@@ -147,3 +151,33 @@ def test_full_batch_256_replicas_sampled(md, tabs, oracle_lib):
         d -= b.box * np.round(d / b.box)
         assert np.max(np.abs(d)) < 1e-9, r
         assert np.max(np.abs(v[off[r]:off[r + 1]] - out["v"])) < 1e-11, r
+
+
+def test_full_batch_256_replicas_mixed_within_float32_bound(md, tabs, oracle_lib):
+    """The mixed form of all 256 replicas in one context, launched as the
+    benchmark launches it (autotuned lanes per atom): for 8 replicas drawn with
+    a fixed seed, every rho_i and force within the float32 bound
+    (mixed_bound.py) of the float64 oracle on the same positions."""
+    reps = configs.config_batch(256)
+    _say(f"[gpu] full batch mixed: {len(reps)} replicas, n={sum(b.n for b in reps)}")
+    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V,
+                       precision=md.MD_MIXED, chunk_steps=100, nbr_capacity=128,
+                       cell_capacity=64)
+    s = md.System(p, tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
+    s.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
+    s.build_neighbors()
+    lpa, _ = s.autotune(5)
+    _say(f"[gpu]   lanes per atom {lpa}")
+    f, rho, _ = (t.cpu().numpy() for t in s.compute_forces())
+    s.close()
+    off = np.concatenate([[0], np.cumsum([b.n for b in reps])])
+    for r in np.sort(np.random.default_rng(12).choice(len(reps), 8, replace=False)):
+        b = reps[r]
+        ref = oracle_lib.forces_at(b.x, b.box, tabs, RC, SKIN)
+        cnt, nbr, _ = oracle_lib.neighbor_list(b.x, b.box, RC + SKIN, cap=128)
+        rho_bound, f_bound = pair_bounds(b.x, b.box, ref["fp"], cnt, nbr)
+        sl = slice(off[r], off[r + 1])
+        assert np.all(np.abs(rho[sl] - ref["rho"]) <= rho_bound), r
+        err = np.linalg.norm(f[sl] - ref["f"], axis=1)
+        assert np.all(err <= f_bound), (r, float(np.max(err / f_bound)))
+        assert np.max(err) > 1e-12  # float32 arithmetic, not the float64 path

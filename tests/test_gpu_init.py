@@ -1,0 +1,180 @@
+"""The boundary's one-call set-up (md_init, md_init_batch, md_workspace_bytes),
+driven through the C ABI with ctypes, against the FP64 oracle; md_step runs of
+any length through captured graphs; the rollback after a binning overflow at a
+re-sort.
+
+Bars as everywhere: positions within 1e-9 A and velocities within 1e-11 A/fs
+of the oracle's velocity-Verlet run, energies within 1e-9 relative; step
+calls of different lengths bitwise equal to one call.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import configs, potential as P
+
+pytestmark = pytest.mark.gpu
+RC, SKIN = P.RC, configs.SKIN
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2405_07898_amd import md as mdmod
+
+    mdmod.lib()
+    return mdmod
+
+
+@pytest.fixture(scope="module")
+def tabs():
+    return P.md_tables()
+
+
+def _params(md, **kw):
+    base = dict(mass=configs.MASS, dt=configs.DT, r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V)
+    base.update(kw)
+    return md.make_params(**base)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _oracle_run(oracle_lib, tabs, b, steps):
+    out = oracle_lib.md_run(b.x, b.v, b.box, tabs, steps, mass=configs.MASS, dt=configs.DT,
+                            r_cut=RC, skin=SKIN, ftm2v=configs.FTM2V, want_energy=True)
+    assert out["code"] == 0
+    return out
+
+
+def _close(x, v, b, out):
+    d = x - out["x"]
+    per = b.box > 0
+    d[:, per] -= b.box[per] * np.round(d[:, per] / b.box[per])
+    assert np.max(np.abs(d)) < 1e-9, np.max(np.abs(d))
+    assert np.max(np.abs(v - out["v"])) < 1e-11, np.max(np.abs(v - out["v"]))
+
+
+@pytest.mark.parametrize("n_rep", [1, 3])
+def test_init_build_step_energy_against_oracle(md, tabs, oracle_lib, n_rep):
+    """md_workspace_bytes -> md_init (one box) or md_init_batch (three boxes,
+    one of them a slab open in x and y) -> md_build_neighbors -> md_step(97)
+    (two 40-step chunks and a 17-step graph) -> md_energy -> md_get_state."""
+    import torch
+
+    lib = md.lib()
+    if n_rep == 1:
+        boxes = [configs.small_box(7, seed=81, temperature=1200.0, sigma_x=0.05)]
+    else:
+        boxes = [configs.small_box(6, seed=82, temperature=900.0, sigma_x=0.05),
+                 configs.slab(7, 6, 5, seed=83, sigma_x=0.05, vacuum=6.0),
+                 configs.ortho_box(5, 6, 7, seed=84, sigma_x=0.05, temperature=2000.0)]
+    _say(f"[gpu] md_init path: {n_rep} box(es), sizes {[b.n for b in boxes]}")
+    p = _params(md, chunk_steps=40)
+    rep_atoms = np.array([b.n for b in boxes], dtype=np.int64)
+    rep_box = np.ascontiguousarray(np.stack([b.box for b in boxes]), dtype=np.float64)
+    nb = lib.md_workspace_bytes(C.byref(p), n_rep, rep_atoms.ctypes.data_as(C.POINTER(C.c_int64)),
+                                _dptr(rep_box))
+    assert nb > 0
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    x = torch.as_tensor(np.concatenate([b.x for b in boxes]), device="cuda")
+    v = torch.as_tensor(np.concatenate([b.v for b in boxes]), device="cuda")
+    sp = [md.Spline(t) for t in tabs]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    ctx = C.c_void_p()
+    if n_rep == 1:
+        rc = lib.md_init(C.byref(ctx), C.byref(p), int(boxes[0].n), _dptr(rep_box), C.byref(sp[0].s),
+                         C.byref(sp[1].s), C.byref(sp[2].s), C.c_void_p(x.data_ptr()),
+                         C.c_void_p(v.data_ptr()), C.c_void_p(ws.data_ptr()), nb,
+                         C.c_void_p(stream.cuda_stream))
+    else:
+        rc = lib.md_init_batch(C.byref(ctx), C.byref(p), n_rep,
+                               rep_atoms.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(rep_box),
+                               C.byref(sp[0].s), C.byref(sp[1].s), C.byref(sp[2].s),
+                               C.c_void_p(x.data_ptr()), C.c_void_p(v.data_ptr()),
+                               C.c_void_p(ws.data_ptr()), nb, C.c_void_p(stream.cuda_stream))
+    assert rc == 0 and ctx.value
+    try:
+        assert lib.md_build_neighbors(ctx) == 0
+        steps = 97
+        assert lib.md_step(ctx, steps) == 0
+        pe = np.zeros(n_rep)
+        ke = np.zeros(n_rep)
+        assert lib.md_energy(ctx, _dptr(pe), _dptr(ke)) == 0
+        xo = torch.empty_like(x)
+        vo = torch.empty_like(v)
+        assert lib.md_get_state(ctx, C.c_void_p(xo.data_ptr()), C.c_void_p(vo.data_ptr()),
+                                None) == 0
+        st = md.md_stats_t()
+        assert lib.md_stats(ctx, C.byref(st)) == 0
+        assert st.steps == steps
+    finally:
+        stream.synchronize()
+        lib.md_destroy(ctx)
+    xo, vo = xo.cpu().numpy(), vo.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(rep_atoms)])
+    for r, b in enumerate(boxes):
+        out = _oracle_run(oracle_lib, tabs, b, steps)
+        _close(xo[off[r]:off[r + 1]].copy(), vo[off[r]:off[r + 1]], b, out)
+        e_pe, e_ke = out["energy"][-1]
+        assert abs(pe[r] - e_pe) <= 1e-9 * abs(e_pe), (r, pe[r], e_pe)
+        assert abs(ke[r] - e_ke) <= 1e-9 * abs(e_ke), (r, ke[r], e_ke)
+
+
+def test_step_calls_of_any_length_equal_one_call(md, tabs):
+    """Step calls of lengths that fill no chunk, leave the odd position buffer
+    current or evict kept graphs run the same kernels in the same order as
+    one call: bitwise the same state."""
+    box = configs.small_box(7, seed=85, temperature=2500.0, sigma_x=0.05)
+    lens = [7, 13, 1, 19, 2, 40, 5, 3, 11, 20, 9, 6, 1]
+    _say(f"[gpu] step lengths {lens} (chunk 20), n={box.n}")
+
+    def run(calls):
+        s = md.System(_params(md, chunk_steps=20), tabs, [box.n], box.box[None, :])
+        s.set_state(box.x, box.v)
+        s.build_neighbors()
+        for n in calls:
+            s.step(n)
+        x, v, f = (t.cpu().numpy() for t in s.get_state())
+        st = s.stats()
+        s.close()
+        return x, v, f, st
+
+    xa, va, fa, sa = run(lens)
+    xb, vb, fb, sb = run([sum(lens)])
+    assert sa["steps"] == sb["steps"] == sum(lens)
+    assert sa["rebuilds"] == sb["rebuilds"] >= 2
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(fa, fb)
+
+
+def test_cell_overflow_at_a_resort_rolls_back_cleanly(md, tabs, oracle_lib):
+    """A hot 432-atom box whose fullest cell grows from 20 to 21 atoms (steps
+    27-68 of the oracle run), cell capacity 20 and a re-sort at every 10-step
+    chunk: md_step reports MD_E_CELL_OVERFLOW and leaves the last clean
+    snapshot, every atom at its own id, equal to the oracle at that step."""
+    box = configs.small_box(6, seed=71, temperature=3000.0, sigma_x=0.05)
+    _say(f"[gpu] cell overflow at a re-sort, n={box.n}")
+    s = md.System(_params(md, chunk_steps=10, sort_every=1, cell_capacity=20), tabs, [box.n],
+                  box.box[None, :])
+    s.set_state(box.x, box.v)
+    s.build_neighbors()
+    rc = s.step(100, check=False)
+    assert rc == md.MD_E_CELL_OVERFLOW, rc
+    st = s.stats()
+    k = int(st["steps"])
+    assert 0 < k < 100 and k % 10 == 0, k
+    x, v, _ = s.get_state(want_f=False)
+    s.close()
+    out = _oracle_run(oracle_lib, tabs, box, k)
+    _close(x.cpu().numpy(), v.cpu().numpy(), box, out)
