@@ -1,10 +1,26 @@
 """Benchmark of the EAM timestep loop on one MI355X.
 
-Default workload: 128,000-atom BCC box (40^3 cells, a = 3.304 A), float64,
-300 K, skin 0.3 A, dt = 1 fs, hipGraph chunks of 100 steps; K timed steps
-after W warm-up steps.  Prints one JSON line (metric: timesteps/s, plus
-atom-steps/s, roofline of the dominant kernel, CPU-oracle baseline and the
-810,448-site float64 / mixed-precision secondary points).
+Headline: the 128,000-atom BCC box (40^3 cells, a = 3.304 A), float64, 300 K,
+skin 0.3 A, dt = 1 fs; W untimed warm-up steps, then exactly K timed steps,
+every one of them inside a captured hipGraph (100-step chunks, the left-over
+steps as one shorter graph).  Prints one JSON line: timesteps/s, atom-steps/s,
+the roofline of the dominant kernel (force pass fused with the integration),
+the measured copy bandwidth, and the secondary workloads:
+  c1_2000          2,000 atoms, float64, 100 steps (launch-latency regime)
+  c2_10000         128,000 atoms, 10,000 steps in 100-step graph chunks:
+                   per-chunk timesteps/s, mean list length and temperature,
+                   energy drift
+  c3_810k          802,344 atoms, float64 and mixed precision, 5,000 steps;
+                   mixed forces at steps 0, 1000, ..., 5000
+  slab_801792      the paper-shaped 256 x 261 x 6 slab, open in x and y
+  half_list_128k   force symmetry (each pair evaluated once)
+  alloy_128k       two atom types
+  perf_model       t = A n_cand + B n_int + C with the candidate filter run
+                   every step, and the list-reuse form
+  batched_256      256 replicas in one launch per pass vs a sequential loop
+  force_matching   gradient evaluations/s of the adjoint
+and the CPU-oracle leg (cpu_baseline): the FP64 oracle timed on the host on
+each workload's sample, and the mixed-precision force error against it.
 
 Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 100]
 """
@@ -25,13 +41,17 @@ sys.path.insert(0, ROOT)
 METRIC = "timesteps/s and atom-steps/s, EAM BCC 128k & 810k atoms, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-KERNEL_SRC = os.path.join(ROOT, "paper_2405_07898_amd", "csrc", "md_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2405_07898_amd", "csrc")
+# the sources that define the dominant kernel (its counters go stale when any changes)
+TRAFFIC_SOURCES = ("md_kernels.hip", "md_device.h", "md_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_integrate_128k_traffic.json")
+CHUNK = 100
 # re-sort atoms by cell every 2 graph chunks (200 steps): the specified potential's
 # lattice melts and its atoms diffuse, so the cell order of the slots decays
 # (measured at 128,000 atoms: 55.6 us/step re-sorting every 2 chunks against
 # 59.9 every 10)
 SORT_EVERY = 2
+SECTIONS = ("c1", "c2", "c3", "slab", "half", "alloy", "perf_model", "batched", "fm")
 
 
 def log(msg: str) -> None:
@@ -42,11 +62,19 @@ def force_pass_bytes(n_atoms: int, n_l: float, mixed: bool) -> float:
     """Algorithmic HBM bytes of one force+integrate launch.
 
     Per atom: x (24) + F' (8, 4 mixed) + list length (4) + list entries (4 n_l)
-    + v read and write (48) + new x (24) + x_ref (24); neighbour gathers are
+    + v read and write (48) + new x (24) + x_ref (24) = 156 + 4 n_l less the
+    force written and read back and x re-read by the separate integration
+    (fused away): 132 + 4 n_l (mixed 128 + 4 n_l).  Neighbour gathers are
     cache-served and not counted.
     """
-    per = 24 + (4 if mixed else 8) + 4 + 4 * n_l + 48 + 24 + 24
+    per = 24 + (4 if mixed else 8) + 4 + 4 * n_l + 48 + 24
     return n_atoms * per
+
+
+def density_pass_bytes(n_atoms: int, n_l: float) -> float:
+    """Algorithmic bytes of one density launch: x (24) + list length (4) + list
+    entries (4 n_l) + F' written (8) = 36 + 4 n_l per atom."""
+    return n_atoms * (36 + 4 * n_l)
 
 
 def force_pass_flops(n_atoms: int, n_l: float, n_int: float) -> float:
@@ -57,36 +85,69 @@ def force_pass_flops(n_atoms: int, n_l: float, n_int: float) -> float:
 
 
 def source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
-def load_traffic(n_launch_atoms: int):
-    """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+def load_traffic(n_atoms: int, n_l: float):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel sources, the same
+    atom count and a mean list length within 2 % of this state's; else None
+    with the reason."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, "no counter file"
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha256") != source_hash() or t.get("n_atoms") != n_launch_atoms:
-        return None
-    return t.get("bytes_per_launch")
+    if t.get("kernel_source_sha256") != source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    if t.get("n_atoms") != n_atoms:
+        return None, "counters taken at another atom count"
+    if abs(t.get("mean_list_length", -1.0) - n_l) > 0.02 * n_l:
+        return None, f"counters taken at mean list length {t.get('mean_list_length')}"
+    return t.get("bytes_per_launch"), t.get("summary")
 
 
-def make_system(md, box, tabs, *, precision, chunk, lpa=0):
+def launch_plan(parity: int, steps: int, chunk: int = CHUNK):
+    """The graph launches md_step makes for `steps` steps starting on position
+    buffer `parity` (whole chunks from buffer 0, the rest as shorter graphs of
+    at most chunk - 1 steps)."""
+    chunks, tails, done = 0, [], 0
+    while done < steps:
+        if parity == 0 and steps - done >= chunk:
+            chunks += 1
+            done += chunk
+        else:
+            n = min(steps - done, chunk - 1)
+            tails.append(n)
+            parity ^= n & 1
+            done += n
+    return {"chunk_graphs": chunks, "chunk_steps": chunk, "shorter_graphs": tails}
+
+
+def make_params(md, *, precision, chunk=CHUNK, lpa=0, **kw):
     from workloads import configs, potential
 
-    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
-                       ftm2v=configs.FTM2V, precision=precision, chunk_steps=chunk,
-                       lanes_per_atom=lpa, nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY)
+    base = dict(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+                ftm2v=configs.FTM2V, precision=precision, chunk_steps=chunk,
+                lanes_per_atom=lpa, nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY)
+    base.update(kw)
+    return md.make_params(**base)
+
+
+def make_system(md, box, tabs, *, precision, chunk=CHUNK, lpa=0, **kw):
+    p = make_params(md, precision=precision, chunk=chunk, lpa=lpa, **kw)
     s = md.System(p, tabs, [box.n], box.box[None, :])
     s.set_state(box.x, box.v)
     s.build_neighbors()
     return s
 
 
-def time_steps(torch, s, steps: int) -> float:
-    """Seconds for `steps` MD steps, bracketed by stream events and syncs."""
+def time_steps(torch, s, steps: int):
+    """Seconds for `steps` MD steps (events on the library stream), bracketed
+    by device synchronisations; and the host wall time."""
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -116,13 +177,21 @@ def time_kernel(torch, s, md, which: int, reps: int) -> float:
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
+def temperature(ke: float, n: int) -> float:
+    from workloads import configs
+
+    return 2.0 * ke / (max(3 * n - 3, 1) * configs.KBOLTZ)
+
+
 def copy_probe(torch, mib: int, reps: int = 5) -> dict:
     """A plain elementwise copy (y = -x, float64) of known size: it reads and
-    writes mib MiB once per launch, so hardware byte counters read on it give
-    the factor between counter units and bytes moved."""
+    writes mib MiB once per launch.  Its rate is the achievable-HBM reference,
+    and hardware byte counters read on it give the factor between counter
+    units and bytes moved."""
     n = mib * (1 << 20) // 8
     src = torch.rand(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -132,80 +201,230 @@ def copy_probe(torch, mib: int, reps: int = 5) -> dict:
     e1.record()
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / reps
+    del src, dst
     return {"bytes_read": n * 8, "bytes_written": n * 8, "launches": reps,
             "avg_us": round(us, 2), "gbs": round(2 * n * 8 / (us * 1e-6) / 1e9, 1)}
 
 
-def cpu_baseline(box, tabs, budget_s: float = 15.0):
-    import oracle
-    from workloads import configs, potential
+# ------------------------------------------------------------------- headline
 
-    oracle.build(force=False)
-    threads = oracle.get_threads()
-    kw = dict(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
-              ftm2v=configs.FTM2V)
-    t0 = time.perf_counter()
-    oracle.md_run(box.x, box.v, box.box, tabs, 5, **kw)
-    per = (time.perf_counter() - t0) / 5.0
-    steps = int(max(5, min(2000, budget_s / max(per, 1e-6))))
-    t0 = time.perf_counter()
-    out = oracle.md_run(box.x, box.v, box.box, tabs, steps, **kw)
-    dt = time.perf_counter() - t0
-    assert out["code"] == 0
-    # the same oracle on one thread (bitwise the same results), a shorter sample
-    oracle.set_threads(1)
-    try:
-        s1 = max(3, steps // (4 * max(threads, 1)))
-        t0 = time.perf_counter()
-        out1 = oracle.md_run(box.x, box.v, box.box, tabs, s1, **kw)
-        dt1 = time.perf_counter() - t0
-    finally:
-        oracle.set_threads(threads)
-    assert out1["code"] == 0
-    return dict(value=steps / dt, unit="timesteps/s", cores=threads, kind="oracle",
-                sample=f"{steps} velocity-Verlet steps of the same {box.n}-atom float64 workload "
-                       f"(first list build included), OpenMP over atoms",
-                atom_steps_per_s=steps * box.n / dt, cpu_model=_cpu_model(),
-                single_thread={"value": s1 / dt1, "unit": "timesteps/s", "steps": s1})
+def bench_headline(torch, md, configs, tabs, args, copy_gbs):
+    box = configs.config_128k() if args.workload == "128k" else configs.config_810k()
+    log(f"workload {args.workload}: n={box.n}; building")
+    s = make_system(md, box, tabs, precision=md.MD_FP64, lpa=args.lpa)
+    if args.lpa == 0:
+        lpa, us = s.autotune(50)
+        log(f"autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
+    else:
+        lpa = args.lpa
+    pe0, ke0 = s.energy()
+    log(f"warmup {args.warmup} steps")
+    s.step(args.warmup)
+    st0 = s.stats()
+    plan = launch_plan(args.warmup & 1, args.steps)
+    log(f"timing {args.steps} steps ({plan})")
+    sec, wall = time_steps(torch, s, args.steps)
+    st1 = s.stats()
+    pe1, ke1 = s.energy()
+    ts = args.steps / sec
+    n_l = st1["list_entries"] / box.n
+    log(f"{ts:.1f} timesteps/s ({sec * 1e3 / args.steps:.4f} ms/step, wall {wall:.3f} s), "
+        f"rebuilds {st1['rebuilds'] - st0['rebuilds']}, mean list {n_l:.2f}")
+    # the dominant kernel at the state the timed steps ended in, on the library stream
+    dens_us = time_kernel(torch, s, md, md.PASS_DENSITY, args.kernel_reps)
+    force_us = time_kernel(torch, s, md, md.PASS_FORCE_RAW, args.kernel_reps)
+    s.close()
+    byts = force_pass_bytes(box.n, n_l, False)
+    flops = force_pass_flops(box.n, n_l, n_l)
+    gbs = byts / (force_us * 1e-6) / 1e9
+    tfl = flops / (force_us * 1e-6) / 1e12
+    dbytes = density_pass_bytes(box.n, n_l)
+    # the roofline that binds: intensity below the float64 ridge -> HBM
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    bound = "hbm" if flops / byts < ridge else "alu"
+    traffic, traffic_note = load_traffic(box.n, n_l)
+    roof = {"bound": bound, "kernel": "k_force_integrate<fp64>",
+            "achieved": round(gbs, 1) if bound == "hbm" else round(tfl, 3),
+            "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_PEAK_TFLOPS,
+            "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+            "frac": round((gbs / HBM_PEAK_GBS) if bound == "hbm" else (tfl / FP64_PEAK_TFLOPS), 4),
+            "traffic": traffic, "traffic_note": traffic_note,
+            "algorithmic_bytes_per_launch": byts, "bytes_per_atom": "132 + 4 n_l",
+            "algorithmic_flops_per_launch": flops, "avg_kernel_us": round(force_us, 3),
+            "frac_of_measured_copy": round(gbs / copy_gbs, 4) if copy_gbs else None,
+            "alu_frac": round(tfl / FP64_PEAK_TFLOPS, 4), "mean_list_length": round(n_l, 3),
+            "density_kernel_us": round(dens_us, 3),
+            "density_hbm_frac": round(dbytes / (dens_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"force pass {force_us:.2f} us -> {gbs:.0f} GB/s ({roof['frac'] * 100:.1f}% HBM), "
+        f"{tfl:.2f} TFLOP/s; density {dens_us:.2f} us")
+    start = "from the 300 K lattice" if args.warmup == 0 else \
+        f"after {args.warmup} warm-up steps from the 300 K lattice"
+    out = {
+        "metric": METRIC, "value": round(ts, 2), "unit": "timesteps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3 / args.steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload] + f"; {args.steps} timed steps {start}",
+                   "n_atoms": box.n, "launch": "hipGraph", **plan, "lanes_per_atom": lpa},
+        "atom_steps_per_s": round(ts * box.n, 1),
+        "energy_drift_per_atom_eV": float(abs((pe1[0] + ke1[0]) - (pe0[0] + ke0[0])) / box.n),
+        "rebuilds_in_timed_region": int(st1["rebuilds"] - st0["rebuilds"]),
+        "mean_list_length": round(n_l, 3),
+        "wall_s_timed": round(wall, 4),
+        "roofline": roof,
+    }
+    return out, box
 
 
-def _cpu_model() -> str:
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+# ------------------------------------------------------------------ secondaries
 
-
-def bench_small(torch, md, configs, tabs):
-    """2,000-atom box, 100-step chunks (launch-latency regime): a captured graph
-    per chunk, and for comparison one persistent cooperative launch per chunk."""
-    from workloads import potential
-
+def bench_c1(torch, md, configs, tabs):
+    """2,000-atom box (launch-latency regime): 100 steps as one captured graph
+    from the prepared state (the workload's own length), a longer 2,000-step
+    window, and one persistent cooperative launch per chunk for comparison."""
     box = configs.config_small()
-    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    s = make_system(md, box, tabs, precision=md.MD_FP64)
     lpa, _ = s.autotune(50)
-    s.step(100)
+    s.close()
+    s = make_system(md, box, tabs, precision=md.MD_FP64, lpa=lpa)
+    pe0, ke0 = s.energy()
+    sec100, _ = time_steps(torch, s, 100)
+    pe1, ke1 = s.energy()
     sec, _ = time_steps(torch, s, 2000)
     st = s.stats()
     s.close()
-    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
-                       ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
-                       lanes_per_atom=8, nbr_capacity=128, cell_capacity=64,
-                       sort_every=SORT_EVERY, launch_mode=md.MD_LAUNCH_PERSISTENT)
-    sp = md.System(p, tabs, [box.n], box.box[None, :])
-    sp.set_state(box.x, box.v)
-    sp.build_neighbors()
+    sp = make_system(md, box, tabs, precision=md.MD_FP64, lpa=8,
+                     launch_mode=md.MD_LAUNCH_PERSISTENT)
     sp.step(100)
     sec_p, _ = time_steps(torch, sp, 2000)
     sp.close()
-    return {"n_atoms": box.n, "steps": 2000, "timesteps_per_s": round(2000 / sec, 1),
-            "atom_steps_per_s": round(2000 / sec * box.n, 1), "lanes_per_atom": lpa,
+    return {"n_atoms": box.n, "lanes_per_atom": lpa,
+            "steps_100": {"timesteps_per_s": round(100 / sec100, 1),
+                          "atom_steps_per_s": round(100 / sec100 * box.n, 1),
+                          "energy_drift_per_atom_eV": float(abs((pe1[0] + ke1[0])
+                                                                - (pe0[0] + ke0[0])) / box.n)},
+            "steps_2000": {"timesteps_per_s": round(2000 / sec, 1),
+                           "atom_steps_per_s": round(2000 / sec * box.n, 1),
+                           "us_per_step": round(sec / 2000 * 1e6, 3)},
             "rebuilds": st["rebuilds"],
             "persistent_launch_timesteps_per_s": round(2000 / sec_p, 1)}
+
+
+def bench_c2_series(torch, md, configs, tabs, steps=10000):
+    """The 128,000-atom workload as specified: 10,000 steps from the 300 K
+    lattice in 100-step graph chunks, each chunk timed with events on the
+    library stream; after each chunk the mean list length of the last build
+    and the temperature.  Energy drift over the whole run."""
+    box = configs.config_128k()
+    s = make_system(md, box, tabs, precision=md.MD_FP64)
+    lpa, _ = s.autotune(50)
+    s.close()
+    s = make_system(md, box, tabs, precision=md.MD_FP64, lpa=lpa)
+    pe0, ke0 = s.energy()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    chunk_ms, n_l, temp, etot = [], [], [], []
+    st_prev = s.stats()
+    rebuilds = []
+    for _ in range(steps // CHUNK):
+        s.stream.synchronize()
+        e[0].record(s.stream)
+        s.step(CHUNK)
+        e[1].record(s.stream)
+        s.stream.synchronize()
+        chunk_ms.append(e[0].elapsed_time(e[1]))
+        st = s.stats()
+        n_l.append(st["list_entries"] / box.n)
+        rebuilds.append(int(st["rebuilds"] - st_prev["rebuilds"]))
+        st_prev = st
+        pe, ke = s.energy()
+        temp.append(temperature(ke[0], box.n))
+        etot.append(pe[0] + ke[0])
+    s.close()
+    total_s = sum(chunk_ms) * 1e-3
+    e0 = pe0[0] + ke0[0]
+    per_chunk = [CHUNK / (ms * 1e-3) for ms in chunk_ms]
+    return {"n_atoms": box.n, "steps": steps, "lanes_per_atom": lpa,
+            "timesteps_per_s": round(steps / total_s, 1),
+            "atom_steps_per_s": round(steps / total_s * box.n, 1),
+            "median_chunk_timesteps_per_s": round(float(np.median(per_chunk)), 1),
+            "energy_drift_per_atom_eV": float(abs(etot[-1] - e0) / box.n),
+            "max_energy_deviation_per_atom_eV": float(np.max(np.abs(np.array(etot) - e0)) / box.n),
+            "rebuilds": int(sum(rebuilds)),
+            "series": {"chunk_timesteps_per_s": [round(v, 1) for v in per_chunk],
+                       "mean_list_length": [round(v, 3) for v in n_l],
+                       "temperature_K": [round(v, 1) for v in temp],
+                       "rebuilds": rebuilds}}
+
+
+def bench_c3(torch, md, configs, tabs, args):
+    """802,344 atoms (74^3 sites, 1 % vacancies, 2,500 K): the float64 and the
+    mixed form, 5,000 steps each.  The mixed run pauses every 1,000 steps
+    (untimed) to export its positions and its forces there, and the float64
+    path's forces on the same positions; the oracle's forces on them come in
+    the CPU leg."""
+    big = configs.config_810k()
+    steps = args.secondary_steps
+    snap_every = max(steps // 5, 1)
+    out = {"n_atoms": big.n, "steps": steps,
+           "workload": "74^3 BCC sites - 1% vacancies, 2500 K"}
+    snaps = []
+    s64_eval = None
+    for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
+        log(f"c3 {name}: n={big.n}")
+        sb = make_system(md, big, tabs, precision=prec, lpa=args.lpa)
+        lpa = args.lpa
+        if args.lpa == 0:
+            lpa, us = sb.autotune(20)
+            log(f"  autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
+        st0 = sb.stats()
+        total = 0.0
+        done = 0
+        while done < steps:
+            if name == "mixed" and done % snap_every == 0:
+                snaps.append(_c3_snapshot(torch, md, sb, big, tabs, done, s64_eval))
+            n = min(snap_every, steps - done)
+            t, _ = time_steps(torch, sb, n)
+            total += t
+            done += n
+        if name == "mixed":
+            snaps.append(_c3_snapshot(torch, md, sb, big, tabs, done, s64_eval))
+        stb = sb.stats()
+        nlb = stb["list_entries"] / big.n
+        fu = time_kernel(torch, sb, md, md.PASS_FORCE_RAW, 50)
+        du = time_kernel(torch, sb, md, md.PASS_DENSITY, 50)
+        b2 = force_pass_bytes(big.n, nlb, prec == md.MD_MIXED)
+        out[name] = {"timesteps_per_s": round(steps / total, 2),
+                     "atom_steps_per_s": round(steps / total * big.n, 1),
+                     "lanes_per_atom": lpa,
+                     "force_pass_us": round(fu, 3),
+                     "force_pass_hbm_frac": round(b2 / (fu * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "density_pass_us": round(du, 3),
+                     "density_pass_hbm_frac": round(density_pass_bytes(big.n, nlb) / (du * 1e-6)
+                                                    / 1e9 / HBM_PEAK_GBS, 4),
+                     "mean_list_length": round(nlb, 3),
+                     "rebuilds": int(stb["rebuilds"] - st0["rebuilds"])}
+        sb.close()
+        if name == "fp64":
+            # a float64 context that evaluates forces on the mixed run's positions
+            s64_eval = md.System(make_params(md, precision=md.MD_FP64, sort_every=0), tabs,
+                                 [big.n], big.box[None, :])
+        log(f"  {out[name]}")
+    s64_eval.close()
+    out["mixed_over_fp64"] = round(out["mixed"]["timesteps_per_s"]
+                                   / out["fp64"]["timesteps_per_s"], 4)
+    return out, big, snaps
+
+
+def _c3_snapshot(torch, md, sm, box, tabs, step, s64):
+    """Positions of the mixed run at `step`, its mixed forces there, and the
+    float64 path's forces on the same positions."""
+    x, _, _ = sm.get_state(want_f=False)
+    fm, _, _ = sm.compute_forces()
+    s64.set_state(x, torch.zeros_like(x))
+    s64.build_neighbors()
+    f64, _, _ = s64.compute_forces()
+    return {"step": step, "x": x.cpu().numpy(), "f_mixed": fm.cpu().numpy(),
+            "f_fp64": f64.cpu().numpy()}
 
 
 def bench_slab(torch, md, configs, tabs, steps):
@@ -213,7 +432,7 @@ def bench_slab(torch, md, configs, tabs, steps):
     256 x 261 x 6 cells, open in x and y, periodic through its thickness, at
     300 K, with the specified potential."""
     box = configs.config_slab_801792()
-    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100)
+    s = make_system(md, box, tabs, precision=md.MD_FP64)
     lpa, _ = s.autotune(20)
     s.step(100)
     st0 = s.stats()
@@ -232,18 +451,10 @@ def bench_half(torch, md, configs, tabs, steps):
     """Force symmetry: the 128,000-atom workload with the half-list form (each
     pair evaluated once, two-phase deterministic reduction), against the
     full-list form on the same box and schedule."""
-    from workloads import potential
-
     box = configs.config_128k()
     out = {"n_atoms": box.n, "steps": steps}
     for name, mode in (("full", md.MD_LIST_FULL), ("half", md.MD_LIST_HALF)):
-        p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
-                           ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
-                           nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY,
-                           list_mode=mode)
-        s = md.System(p, tabs, [box.n], box.box[None, :])
-        s.set_state(box.x, box.v)
-        s.build_neighbors()
+        s = make_system(md, box, tabs, precision=md.MD_FP64, list_mode=mode)
         lpa, _ = s.autotune(20)
         s.step(100)
         st0 = s.stats()
@@ -263,9 +474,7 @@ def bench_alloy(torch, md, configs, potential, steps):
     """Several atom types: the 128,000-atom random equiatomic binary alloy (per-type
     rho and F, per-pair phi, per-type masses), same schedule as the main workload."""
     box = configs.config_alloy_128k()
-    p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
-                       ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
-                       nbr_capacity=128, cell_capacity=64, sort_every=SORT_EVERY, n_types=2)
+    p = make_params(md, precision=md.MD_FP64, n_types=2)
     s = md.System(p, potential.alloy_tables(), [box.n], box.box[None, :],
                   masses=potential.ALLOY_MASS)
     s.set_state(box.x, box.v)
@@ -287,11 +496,41 @@ def bench_alloy(torch, md, configs, potential, steps):
             "mean_list_length": round(st1["list_entries"] / box.n, 3)}
 
 
-def perf_model(torch, md, configs, tabs, steps: int = 1000):
-    """Linear model of the step time at fixed N, t = A n_l + B n_int + C (the
-    paper's Eq. linearmodel / Table "regression", with list entries standing
-    in for candidates): dt = 0 sweeps over the interaction cutoff and the skin
-    on the 128,000-atom lattice, so the list never changes."""
+def _candidates_per_atom(box, rl):
+    """Mean number of atoms in the 27 cells around each atom's cell (itself
+    included): the candidates the list build tests."""
+    L = box.box
+    nc = np.floor(L / rl).astype(np.int64)
+    c = np.minimum((box.x * (nc / L)).astype(np.int64), nc - 1)
+    flat = (c[:, 2] * nc[1] + c[:, 1]) * nc[0] + c[:, 0]
+    occ = np.bincount(flat, minlength=int(np.prod(nc))).reshape(nc[2], nc[1], nc[0])
+    s = np.zeros_like(occ)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                s += np.roll(occ, (dz, dy, dx), axis=(0, 1, 2))
+    return float((occ * s).sum() / box.n)
+
+
+def _fit(rows, cols, target):
+    m = np.array(rows)
+    X = np.column_stack([m[:, c] for c in cols] + [np.ones(len(m))])
+    coef, *_ = np.linalg.lstsq(X, m[:, target], rcond=None)
+    pred = X @ coef
+    r2 = 1.0 - np.sum((m[:, target] - pred) ** 2) / np.sum((m[:, target] - m[:, target].mean()) ** 2)
+    return coef, float(r2)
+
+
+def perf_model(torch, md, configs, tabs, steps: int = 1000, reps: int = 20):
+    """Linear models of the step time at fixed N (the paper's Eq. linearmodel /
+    Table "regression": t = A n_cand + B n_int + C), from dt = 0 sweeps of the
+    interaction cutoff and the skin on the 128,000-atom lattice.
+
+    - every_step: the candidate filter runs every step, as on the wafer: binning
+      + list build + density + force (each kernel timed over `reps`
+      back-to-back launches), fitted to candidates and interactions per atom;
+    - list_reuse: md_step with the list kept (dt = 0 never triggers a rebuild),
+      fitted to list entries and interactions per atom."""
     from workloads import potential
 
     box = configs.config_128k()
@@ -299,7 +538,7 @@ def perf_model(torch, md, configs, tabs, steps: int = 1000):
     for rc in (3.0, 3.5, 4.0, 5.0):
         for skin in (0.3, 0.8, 1.4, 2.2):
             p = md.make_params(mass=configs.MASS, dt=0.0, r_cut=rc, skin=skin,
-                               ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=100,
+                               ftm2v=configs.FTM2V, precision=md.MD_FP64, chunk_steps=CHUNK,
                                lanes_per_atom=2, nbr_capacity=160, cell_capacity=64,
                                sort_every=0)
             s = md.System(p, tabs, [box.n], box.box[None, :])
@@ -308,6 +547,11 @@ def perf_model(torch, md, configs, tabs, steps: int = 1000):
             s.step(200)
             sec, _ = time_steps(torch, s, steps)
             n_l = s.stats()["list_entries"] / box.n
+            t_build = time_kernel(torch, s, md, md.PASS_BUILD, reps)
+            t_bin1 = time_kernel(torch, s, md, md.PASS_BIN, reps)  # reps binnings + one build
+            t_bin = t_bin1 - t_build / reps
+            t_dens = time_kernel(torch, s, md, md.PASS_DENSITY, reps)
+            t_frc = time_kernel(torch, s, md, md.PASS_FORCE_RAW, reps)
             cnt, nbr = s.neighbors(160)
             s.close()
             # interactions (r < r_cut) of a fixed sample of atoms, from the exported list
@@ -319,56 +563,78 @@ def perf_model(torch, md, configs, tabs, steps: int = 1000):
                 d = box.x[na[:ca]] - box.x[a]
                 d -= box.box * np.round(d / box.box)
                 n_int += int(np.count_nonzero((d * d).sum(1) < rc * rc))
-            rows.append((n_l, n_int / len(pick), sec / steps * 1e6, rc, skin))
-    m = np.array(rows)
-    X = np.column_stack([m[:, 0], m[:, 1], np.ones(len(m))])
-    coef, *_ = np.linalg.lstsq(X, m[:, 2], rcond=None)
-    pred = X @ coef
-    r2 = 1.0 - np.sum((m[:, 2] - pred) ** 2) / np.sum((m[:, 2] - m[:, 2].mean()) ** 2)
-    return {"n_atoms": box.n, "steps_per_point": steps, "lanes_per_atom": 2,
-            "us_per_step_per_list_entry": round(float(coef[0]), 4),
-            "us_per_step_per_interaction": round(float(coef[1]), 4),
-            "us_per_step_fixed": round(float(coef[2]), 3),
-            "ns_per_atom_list_entry": round(float(coef[0]) * 1e3 / box.n, 6),
-            "ns_per_atom_interaction": round(float(coef[1]) * 1e3 / box.n, 6),
-            "r2": round(float(r2), 5),
-            "points": [{"r_cut": r[3], "skin": r[4], "n_l": round(r[0], 3),
-                        "n_int": round(r[1], 3), "us_per_step": round(r[2], 3)} for r in rows]}
+            n_c = _candidates_per_atom(box, rc + skin)
+            rows.append((n_c, n_l, n_int / len(pick), t_bin + t_build + t_dens + t_frc,
+                         sec / steps * 1e6, rc, skin, t_build, t_bin, t_dens, t_frc))
+    ce, r2e = _fit(rows, (0, 2), 3)
+    cr, r2r = _fit(rows, (1, 2), 4)
+    ns = 1e3 / box.n  # us per step -> ns per atom-step
+    return {"n_atoms": box.n, "lanes_per_atom": 2,
+            "every_step": {"us_per_step_per_candidate": round(float(ce[0]), 5),
+                           "us_per_step_per_interaction": round(float(ce[1]), 5),
+                           "us_per_step_fixed": round(float(ce[2]), 3),
+                           "ns_per_atom_candidate": round(float(ce[0]) * ns, 7),
+                           "ns_per_atom_interaction": round(float(ce[1]) * ns, 7),
+                           "ns_per_atom_fixed": round(float(ce[2]) * ns, 6), "r2": round(r2e, 5)},
+            "list_reuse": {"us_per_step_per_list_entry": round(float(cr[0]), 5),
+                           "us_per_step_per_interaction": round(float(cr[1]), 5),
+                           "us_per_step_fixed": round(float(cr[2]), 3), "r2": round(r2r, 5)},
+            "paper_wse_ns": {"candidate": 26.6, "interaction": 71.4, "fixed": 574},
+            "points": [{"r_cut": r[5], "skin": r[6], "n_cand": round(r[0], 2),
+                        "n_l": round(r[1], 3), "n_int": round(r[2], 3),
+                        "us_every_step": round(r[3], 3), "us_list_reuse": round(r[4], 3),
+                        "us_build": round(r[7], 3), "us_bin": round(r[8], 3),
+                        "us_density": round(r[9], 3), "us_force": round(r[10], 3)}
+                       for r in rows]}
 
 
 def bench_batched(torch, md, configs, tabs, args):
     """256 replicas (5-20 cells, 0-2 % vacancies, 300-2000 K) in one launch per pass,
     against a sequential loop of single-replica contexts."""
-    from workloads import potential
-
     reps = configs.config_batch(256)
     n_tot = sum(b.n for b in reps)
     res = {"n_replicas": len(reps), "n_atoms_total": n_tot}
-    for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
-        p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC,
-                           skin=configs.SKIN, ftm2v=configs.FTM2V, precision=prec,
-                           chunk_steps=100, nbr_capacity=128, cell_capacity=64)
+    sizes = np.array([b.n for b in reps])
+    cls = np.where(sizes <= 2048, 0, np.where(sizes <= 8192, 1, 2))
+    x0 = np.concatenate([b.x for b in reps])
+    v0 = np.concatenate([b.v for b in reps])
+
+    def fresh(p):
         s = md.System(p, tabs, [b.n for b in reps], np.stack([b.box for b in reps]))
-        s.set_state(np.concatenate([b.x for b in reps]), np.concatenate([b.v for b in reps]))
+        s.set_state(x0, v0)
         s.build_neighbors()
-        lpa, _ = s.autotune(20)
-        s.step(100)
-        steps = args.batched_steps
-        sec, _ = time_steps(torch, s, steps)
+        return s
+
+    steps = args.batched_steps
+    for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
+        p = make_params(md, precision=prec, sort_every=1)
+        s = fresh(p)
+        lpa, us = s.autotune(20)
+        sched = s.replica_schedule()
         s.close()
-        res[name] = {"steps": steps, "lanes_per_atom": lpa,
-                     "timesteps_per_s": round(steps / sec, 2),
-                     "atom_steps_per_s": round(steps * n_tot / sec, 1)}
+        res[name] = {"steps": steps, "lanes_per_atom_uniform_best": lpa,
+                     "lanes_per_atom_by_size_class": {
+                         c: int(sched[cls == k][0]) for k, c in
+                         enumerate(("<=2048 atoms", "<=8192 atoms", ">8192 atoms"))
+                         if np.any(cls == k)}}
+        # the autotuned schedule and the single best value for all, each from the
+        # same initial state over the same steps
+        for mode, set_sched in (("autotuned", lambda q: q.set_replica_schedule(sched)),
+                                ("uniform", lambda q: q.set_schedule(lpa))):
+            s = fresh(p)
+            set_sched(s)
+            s.step(100)
+            sec, _ = time_steps(torch, s, steps)
+            s.close()
+            res[name][mode] = {"timesteps_per_s": round(steps / sec, 2),
+                               "atom_steps_per_s": round(steps * n_tot / sec, 1)}
+        res[name]["timesteps_per_s"] = res[name]["autotuned"]["timesteps_per_s"]
+        res[name]["atom_steps_per_s"] = res[name]["autotuned"]["atom_steps_per_s"]
     # sequential per-replica loop (float64), same kernels, one context per replica
     seq_steps = args.sequential_steps
     systems = []
     for b in reps:
-        p = md.make_params(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC,
-                           skin=configs.SKIN, ftm2v=configs.FTM2V, chunk_steps=50,
-                           nbr_capacity=128, cell_capacity=64)
-        s = md.System(p, tabs, [b.n], b.box[None, :])
-        s.set_state(b.x, b.v)
-        s.build_neighbors()
+        s = make_system(md, b, tabs, precision=md.MD_FP64, chunk=50, sort_every=1)
         s.step(50)
         systems.append(s)
     torch.cuda.synchronize()
@@ -415,16 +681,130 @@ def bench_fm(torch, md, configs, potential, tabs):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     prob.close()
+    problem = {"x": x, "fref": fref.cpu().numpy(), "boxes": np.stack([b.box for b in boxes]),
+               "offsets": np.concatenate([[0], np.cumsum([b.n for b in boxes])]), "tabs": ftabs}
     return {"n_configs": 64, "n_atoms_total": int(x.shape[0]),
             "gradient_evaluations_per_s": round(reps / sec, 2),
-            "ms_per_gradient_evaluation": round(sec / reps * 1e3, 4)}
+            "ms_per_gradient_evaluation": round(sec / reps * 1e3, 4)}, problem
+
+
+# ------------------------------------------------------------- CPU oracle leg
+
+def cpu_baseline(box, tabs, budget_s: float = 15.0):
+    """The FP64 oracle on the headline workload: OpenMP over atoms on the
+    host's cores, then a shorter single-thread sample."""
+    import oracle
+    from workloads import configs, potential
+
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    kw = dict(mass=configs.MASS, dt=configs.DT, r_cut=potential.RC, skin=configs.SKIN,
+              ftm2v=configs.FTM2V)
+    t0 = time.perf_counter()
+    oracle.md_run(box.x, box.v, box.box, tabs, 5, **kw)
+    per = (time.perf_counter() - t0) / 5.0
+    steps = int(max(5, min(2000, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    out = oracle.md_run(box.x, box.v, box.box, tabs, steps, **kw)
+    dt = time.perf_counter() - t0
+    assert out["code"] == 0
+    # the same oracle on one thread (bitwise the same results), a shorter sample
+    oracle.set_threads(1)
+    try:
+        s1 = max(3, steps // (4 * max(threads, 1)))
+        t0 = time.perf_counter()
+        out1 = oracle.md_run(box.x, box.v, box.box, tabs, s1, **kw)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    assert out1["code"] == 0
+    return dict(value=steps / dt, unit="timesteps/s", cores=threads, kind="oracle",
+                sample=f"{steps} velocity-Verlet steps of the same {box.n}-atom float64 workload "
+                       f"(first list build included), OpenMP over atoms",
+                atom_steps_per_s=steps * box.n / dt, cpu_model=_cpu_model(),
+                single_thread={"value": s1 / dt1, "unit": "timesteps/s", "steps": s1})
+
+
+def cpu_c1(tabs):
+    """The oracle on the 2,000-atom workload: all of its 100 steps."""
+    import oracle
+    from workloads import configs, potential
+
+    box = configs.config_small()
+    t0 = time.perf_counter()
+    out = oracle.md_run(box.x, box.v, box.box, tabs, 100, mass=configs.MASS, dt=configs.DT,
+                        r_cut=potential.RC, skin=configs.SKIN, ftm2v=configs.FTM2V)
+    dt = time.perf_counter() - t0
+    assert out["code"] == 0
+    return {"steps": 100, "timesteps_per_s": round(100 / dt, 2),
+            "atom_steps_per_s": round(100 * box.n / dt, 1), "cores": oracle.get_threads()}
+
+
+def cpu_c3(tabs, big, snaps):
+    """The oracle on the 802,344-atom workload: 10 velocity-Verlet steps (rate),
+    and its forces on the mixed run's positions at each snapshot, where the
+    mixed and the float64 GPU forces are compared with it."""
+    import oracle
+    from workloads import configs, potential
+
+    t0 = time.perf_counter()
+    out = oracle.md_run(big.x, big.v, big.box, tabs, 10, mass=configs.MASS, dt=configs.DT,
+                        r_cut=potential.RC, skin=configs.SKIN, ftm2v=configs.FTM2V)
+    dt = time.perf_counter() - t0
+    assert out["code"] == 0
+    rows = []
+    t_eval = 0.0
+    for sn in snaps:
+        t0 = time.perf_counter()
+        ref = oracle.forces_at(sn["x"], big.box, tabs, potential.RC, configs.SKIN)
+        t_eval += time.perf_counter() - t0
+        fr = ref["f"]
+        rms_f = float(np.sqrt(np.mean(np.sum(fr * fr, axis=1))))
+        em = np.linalg.norm(sn["f_mixed"] - fr, axis=1)
+        e64 = np.linalg.norm(sn["f_fp64"] - fr, axis=1)
+        rows.append({"step": sn["step"], "force_rms_eVA": rms_f,
+                     "mixed_max_eVA": float(em.max()),
+                     "mixed_rms_eVA": float(np.sqrt(np.mean(em * em))),
+                     "mixed_max_rel_to_rms_force": float(em.max() / rms_f),
+                     "fp64_gpu_max_eVA": float(e64.max()),
+                     "fp64_gpu_max_rel_to_max_force": float(e64.max()
+                                                            / np.linalg.norm(fr, axis=1).max())})
+    return {"oracle_steps": 10, "oracle_timesteps_per_s": round(10 / dt, 3),
+            "oracle_atom_steps_per_s": round(10 * big.n / dt, 1),
+            "oracle_snapshot_force_evaluations": len(snaps),
+            "oracle_s_per_force_evaluation": round(t_eval / max(len(snaps), 1), 3),
+            "cores": oracle.get_threads(), "force_error_vs_oracle": rows}
+
+
+def cpu_c5(problem):
+    """The oracle's force-matching loss and reverse-mode gradient over the same
+    64 configurations: one gradient evaluation, timed."""
+    import oracle
+
+    t0 = time.perf_counter()
+    loss, _, _ = oracle.fm_loss_grad(problem["x"], problem["offsets"], problem["boxes"],
+                                     problem["tabs"], problem["fref"])
+    dt = time.perf_counter() - t0
+    return {"gradient_evaluations_per_s": round(1.0 / dt, 3), "s_per_gradient_evaluation":
+            round(dt, 4), "loss": loss, "cores": oracle.get_threads()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 WORKLOADS = {
     "128k": "EAM BCC 40x40x40 cells (128,000 atoms), a=3.304 A, 300 K, skin 0.3 A, dt 1 fs, "
-            "NVE, float64, hipGraph chunks of 100 steps",
+            "NVE, float64",
     "810k": "EAM BCC 74x74x74 cells minus 1% vacancies (802,344 atoms), a=3.304 A, 2,500 K, "
-            "skin 0.3 A, dt 1 fs, NVE, float64, hipGraph chunks of 100 steps",
+            "skin 0.3 A, dt 1 fs, NVE, float64",
 }
 
 
@@ -435,13 +815,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma-separated secondary workloads to run")
     ap.add_argument("--secondary-steps", type=int, default=5000)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--lpa", type=int, default=0)
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--sequential-steps", type=int, default=20)
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (calibrates HBM counters)")
+    ap.add_argument("--copy-probe-mib", type=int, default=512,
+                    help="size of the plain device copy that measures achievable HBM bandwidth")
     ap.add_argument("--workload", choices=("128k", "810k"), default="128k",
                     help="the timed workload (810k: for profiling at the paper's scale; the "
                          "reported metric is the 128k one)")
@@ -463,132 +845,58 @@ def main() -> int:
     md.lib()
     tabs = potential.md_tables()
     if args.fm_only:
-        print(json.dumps({"force_matching": bench_fm(torch, md, configs, potential, tabs)}),
-              flush=True)
+        res, _ = bench_fm(torch, md, configs, potential, tabs)
+        print(json.dumps({"force_matching": res}), flush=True)
         return 0
-    box = configs.config_128k() if args.workload == "128k" else configs.config_810k()
-    log(f"workload {args.workload}: n={box.n} box={box.box[0]:.3f} A; building")
-    s = make_system(md, box, tabs, precision=md.MD_FP64, chunk=100, lpa=args.lpa)
-    if args.lpa == 0:
-        lpa, us = s.autotune(50)
-        log(f"autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
-    pe0, ke0 = s.energy()
-    log(f"warmup {args.warmup} steps")
-    s.step(args.warmup)
-    st0 = s.stats()
-    log(f"timing {args.steps} steps")
-    sec, wall = time_steps(torch, s, args.steps)
-    st1 = s.stats()
-    pe1, ke1 = s.energy()
-    ts = args.steps / sec
-    n_l = st1["list_entries"] / box.n
-    log(f"{ts:.1f} timesteps/s ({sec * 1e3 / args.steps:.4f} ms/step, wall {wall:.3f} s), "
-        f"rebuilds {st1['rebuilds'] - st0['rebuilds']}, mean list {n_l:.2f}")
-
-    # dominant kernel: force + integrate, timed per launch on the library stream
-    dens_us = time_kernel(torch, s, md, md.PASS_DENSITY, args.kernel_reps)
-    force_us = time_kernel(torch, s, md, md.PASS_FORCE_RAW, args.kernel_reps)
-    byts = force_pass_bytes(box.n, n_l, False)
-    flops = force_pass_flops(box.n, n_l, n_l)
-    gbs = byts / (force_us * 1e-6) / 1e9
-    tfl = flops / (force_us * 1e-6) / 1e12
-    # the roofline that binds: intensity below the float64 ridge -> HBM
-    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    bound = "hbm" if flops / byts < ridge else "alu"
-    traffic = load_traffic(box.n)
-    roof = {"bound": bound, "kernel": "k_force_integrate<fp64>",
-            "achieved": round(gbs, 1) if bound == "hbm" else round(tfl, 3),
-            "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_PEAK_TFLOPS,
-            "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
-            "frac": round((gbs / HBM_PEAK_GBS) if bound == "hbm" else (tfl / FP64_PEAK_TFLOPS), 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": byts, "algorithmic_flops_per_launch": flops,
-            "avg_kernel_us": round(force_us, 3),
-            "alu_frac": round(tfl / FP64_PEAK_TFLOPS, 4), "mean_list_length": round(n_l, 3),
-            "density_kernel_us": round(dens_us, 3)}
-    log(f"force pass {force_us:.2f} us -> {gbs:.0f} GB/s ({roof['frac'] * 100:.1f}% HBM), "
-        f"{tfl:.2f} TFLOP/s; density {dens_us:.2f} us")
-    s.close()
-
-    out = {
-        "metric": METRIC, "value": round(ts, 2), "unit": "timesteps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3 / args.steps, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
-                   "n_atoms": box.n, "chunk_steps": 100},
-        "atom_steps_per_s": round(ts * box.n, 1),
-        "energy_drift_per_atom_eV": float(abs((pe1[0] + ke1[0]) - (pe0[0] + ke0[0])) / box.n),
-        "rebuilds_in_timed_region": int(st1["rebuilds"] - st0["rebuilds"]),
-        "wall_s_timed": round(wall, 4),
-        "roofline": roof,
-    }
-
-    if not args.no_secondary:
-        big = configs.config_810k()
-        sec_out = {}
-        for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
-            log(f"secondary 810k {name}: n={big.n}")
-            sb = make_system(md, big, tabs, precision=prec, chunk=100, lpa=args.lpa)
-            if args.lpa == 0:
-                lpa, us = sb.autotune(20)
-                log(f"  autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
-            sb.step(100)
-            t2, _ = time_steps(torch, sb, args.secondary_steps)
-            stb = sb.stats()
-            nlb = stb["list_entries"] / big.n
-            fu = time_kernel(torch, sb, md, md.PASS_FORCE_RAW, 50)
-            b2 = force_pass_bytes(big.n, nlb, prec == md.MD_MIXED)
-            sec_out[name] = {"timesteps_per_s": round(args.secondary_steps / t2, 2),
-                             "atom_steps_per_s": round(args.secondary_steps / t2 * big.n, 1),
-                             "force_pass_us": round(fu, 3),
-                             "force_pass_hbm_frac": round(b2 / (fu * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                             "mean_list_length": round(nlb, 3), "rebuilds": stb["rebuilds"]}
-            if name == "fp64":
-                f64, _, _ = sb.compute_forces()
-                x64, _, _ = sb.get_state(want_f=False)
-            else:
-                # mixed forces at the float64 run's positions, against its float64 forces
-                sb.set_state(x64, torch.zeros_like(x64))
-                sb.build_neighbors()
-                fm, _, _ = sb.compute_forces()
-                err = (fm - f64).norm(dim=1)
-                rms = f64.norm(dim=1).pow(2).mean().sqrt().item()
-                sec_out[name]["force_err_vs_fp64_max_eVA"] = err.max().item()
-                sec_out[name]["force_err_vs_fp64_rms_eVA"] = err.pow(2).mean().sqrt().item()
-                sec_out[name]["force_rms_eVA"] = rms
-            sb.close()
-            log(f"  {sec_out[name]}")
-        out["secondary_810k"] = {"n_atoms": big.n, "steps": args.secondary_steps,
-                                 "workload": "74^3 BCC sites - 1% vacancies, 2500 K", **sec_out}
-
-    if not args.no_secondary:
-        log("secondary slab 801,792 atoms")
-        out["secondary_slab_801792"] = bench_slab(torch, md, configs, tabs, args.secondary_steps)
-        log(f"  slab: {out['secondary_slab_801792']}")
-        out["secondary_half_list_128k"] = bench_half(torch, md, configs, tabs, 5000)
-        log(f"  half list: {out['secondary_half_list_128k']}")
-        out["secondary_alloy_128k"] = bench_alloy(torch, md, configs, potential, 5000)
-        log(f"  binary alloy: {out['secondary_alloy_128k']}")
-        out["secondary_small_2000"] = bench_small(torch, md, configs, tabs)
-        out["secondary_perf_model"] = perf_model(torch, md, configs, tabs)
-        pm = out["secondary_perf_model"]
-        log(f"  perf model: t = {pm['us_per_step_per_list_entry']} n_l + "
-            f"{pm['us_per_step_per_interaction']} n_int + {pm['us_per_step_fixed']} us, "
-            f"r2 {pm['r2']}")
-        log(f"  small: {out['secondary_small_2000']}")
-        out["secondary_batched_256"] = bench_batched(torch, md, configs, tabs, args)
-        log(f"  batched: {out['secondary_batched_256']}")
-        out["secondary_force_matching"] = bench_fm(torch, md, configs, potential, tabs)
-        log(f"  force matching: {out['secondary_force_matching']}")
-
-    if args.copy_probe_mib > 0:
-        out["copy_probe"] = copy_probe(torch, args.copy_probe_mib)
-        log(f"copy probe: {out['copy_probe']}")
+    copy = copy_probe(torch, args.copy_probe_mib) if args.copy_probe_mib > 0 else None
+    if copy:
+        log(f"copy probe: {copy}")
+    out, box = bench_headline(torch, md, configs, tabs, args, copy["gbs"] if copy else None)
+    if copy:
+        out["copy_probe"] = copy
+    sections = set() if args.no_secondary else set(args.sections.split(","))
+    big, snaps, fm_problem = None, [], None
+    if "c1" in sections:
+        out["c1_2000"] = bench_c1(torch, md, configs, tabs)
+        log(f"  c1: {out['c1_2000']}")
+    if "c2" in sections:
+        out["c2_10000"] = bench_c2_series(torch, md, configs, tabs)
+        log(f"  c2: {({k: v for k, v in out['c2_10000'].items() if k != 'series'})}")
+    if "c3" in sections:
+        out["c3_810k"], big, snaps = bench_c3(torch, md, configs, tabs, args)
+    if "slab" in sections:
+        log("slab 801,792 atoms")
+        out["slab_801792"] = bench_slab(torch, md, configs, tabs, args.secondary_steps)
+        log(f"  slab: {out['slab_801792']}")
+    if "half" in sections:
+        out["half_list_128k"] = bench_half(torch, md, configs, tabs, 5000)
+        log(f"  half list: {out['half_list_128k']}")
+    if "alloy" in sections:
+        out["alloy_128k"] = bench_alloy(torch, md, configs, potential, 5000)
+        log(f"  binary alloy: {out['alloy_128k']}")
+    if "perf_model" in sections:
+        out["perf_model"] = perf_model(torch, md, configs, tabs)
+        pm = out["perf_model"]
+        log(f"  perf model: every step {pm['every_step']}; list reuse {pm['list_reuse']}")
+    if "batched" in sections:
+        out["batched_256"] = bench_batched(torch, md, configs, tabs, args)
+        log(f"  batched: {out['batched_256']}")
+    if "fm" in sections:
+        out["force_matching"], fm_problem = bench_fm(torch, md, configs, potential, tabs)
+        log(f"  force matching: {out['force_matching']}")
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(box, tabs)
+        log(f"  {out['cpu_baseline']}")
+        if "c1" in sections:
+            out["cpu_baseline"]["c1_2000"] = cpu_c1(tabs)
+        if snaps:
+            c3 = cpu_c3(tabs, big, snaps)
+            out["c3_810k"]["force_error_vs_oracle"] = c3.pop("force_error_vs_oracle")
+            out["cpu_baseline"]["c3_810k"] = c3
+        if fm_problem is not None:
+            out["cpu_baseline"]["c5_force_matching"] = cpu_c5(fm_problem)
         log(f"  {out['cpu_baseline']}")
 
     print(json.dumps(out), flush=True)

@@ -290,13 +290,31 @@ md_status md_launch_pass(md_ctx* ctx, int32_t pass, int32_t reps);
  * identical up to that reduction order.  Drops the captured step graphs. */
 md_status md_set_schedule(md_ctx* ctx, int32_t lanes_per_atom);
 
+/* Per-replica schedule of a batched context (the batched form's multi-core
+ * workers, Sec. VI-A): lanes[r] (host, n_rep values of 1, 2, 4 or 8) lanes
+ * per atom for replica r, all in the same launch per pass.  The pair passes
+ * then take work in pair tiles of 64 / lanes[r] atoms of one replica, one
+ * wave per tile.  A replica's results depend only on its own value: bitwise
+ * those of the replica alone with md_set_schedule(lanes[r]).  All values
+ * equal: the same as md_set_schedule.  Full list, one atom type and graph
+ * launches only (else MD_E_ARG).  Drops the captured step graphs. */
+md_status md_set_replica_schedule(md_ctx* ctx, const int32_t* lanes);
+
+/* Lanes per atom of each replica (host, n_rep values). */
+md_status md_get_replica_schedule(md_ctx* ctx, int32_t* lanes);
+
 /* Autotuner: times reps rounds of the step's density and force-plus-update
  * kernels at the current state for every lanes-per-atom choice (HIP events on
  * the context stream, two sweeps, the faster sweep of each choice kept),
  * keeps the fastest and reports it in microseconds per round (either pointer
- * may be NULL).  Positions, velocities and the step count come back from the
- * rollback snapshot, which then holds the current state.  Requires
- * md_build_neighbors. */
+ * may be NULL).  With several replicas (full list, one atom type, graph
+ * launches) it then searches one value per replica size class (up to 2,048
+ * atoms, up to 8,192, larger), class by class from the uniform choice in two
+ * passes, and keeps that per-replica schedule if it is faster
+ * (md_get_replica_schedule tells; *best_lanes_per_atom stays the best
+ * uniform value, *best_us the time of the kept schedule).  Positions,
+ * velocities and the step count come back from the rollback snapshot, which
+ * then holds the current state.  Requires md_build_neighbors. */
 md_status md_autotune(md_ctx* ctx, int32_t reps, int32_t* best_lanes_per_atom, float* best_us);
 
 /* Last error text of this context (or of the library when ctx is NULL). */

@@ -123,6 +123,10 @@ struct md_ctx {
   int32_t* status = nullptr;
   int cur = 0;
   int lpa = 1;
+  // per-replica lanes per atom (empty: every replica takes `lpa`); the pair
+  // passes then walk the pair-tile table
+  std::vector<int32_t> rep_lpa;
+  PairTile* ptile_buf = nullptr;
   bool half = false;    // half-list pair passes
   bool multi = false;   // several atom types
   MultiTables mt{};
@@ -188,11 +192,12 @@ struct Buffers {
   double *rho, *epair;
   int32_t *id, *cell_of, *cnt;
   uint32_t* nbr;
-  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *status, *rflag;
+  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *cell_order, *status, *rflag;
   double4 *sort_pos, *sort_vel;
   int32_t* sort_id;
   double4 *snap_pos, *snap_vel;
   double *partial, *energy;
+  PairTile* ptiles;
   // multi-species form only
   double4 *m_rho_seg, *m_phi_val, *m_rho_val, *m_emb_val;
   double* m_frow;
@@ -249,6 +254,7 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.bin_idx = c.take<int32_t>((size_t)s.cells * p->cell_capacity);
   o.cell_start = c.take<int32_t>((size_t)s.cells + 1);
   o.cell_stat = c.take<int32_t>(3 * (size_t)s.cells);
+  o.cell_order = c.take<int32_t>((size_t)s.cells);
   o.status = c.take<int32_t>(SW_WORDS);
   o.rflag = c.take<int32_t>(3 * (size_t)n_rep);
   o.sort_pos = c.take<double4>(N);
@@ -258,6 +264,8 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.snap_vel = c.take<double4>(N);
   o.partial = c.take<double>(2 * s.atile_blocks);
   o.energy = c.take<double>(2 * (size_t)n_rep);
+  // pair tiles of a per-replica schedule: at most 8 per atom tile, and padding
+  o.ptiles = c.take<PairTile>(8 * s.atile_blocks + 8 * (size_t)n_rep + kXcd);
   o.m_rho_seg = o.m_phi_val = o.m_rho_val = o.m_emb_val = nullptr;
   o.m_frow = nullptr;
   o.type = o.type_orig = o.sort_type = nullptr;
@@ -352,6 +360,9 @@ hipError_t density_pass(md_ctx* c, const State& s, int lpa, const double4* pos,
   if (c->half)
     return launch_half_density(c->L, c->g, s, c->t, pos, cond, false, clear_flag, rclear,
                                c->sz.cells, want_rho);
+  if (lpa == 0)
+    return launch_density_dyn(c->L, c->g, s, c->t, c->p.precision, pos, cond, clear_flag, rclear,
+                              c->sz.cells, want_rho);
   return launch_density(c->L, c->g, s, c->t, c->p.precision, lpa, pos, cond, clear_flag, rclear,
                         c->sz.cells, want_rho);
 }
@@ -364,6 +375,9 @@ hipError_t force_integrate_pass(md_ctx* c, const State& s, int lpa, const double
   if (c->half)
     return launch_half_force_integrate(c->L, c->g, s, c->t, pos_in, pos_out, flag_next,
                                        rflag_next);
+  if (lpa == 0)
+    return launch_force_integrate_dyn(c->L, c->g, s, c->t, c->p.precision, pos_in, pos_out,
+                                      flag_next, rflag_next);
   return launch_force_integrate(c->L, c->g, s, c->t, c->p.precision, lpa, pos_in, pos_out,
                                 flag_next, rflag_next);
 }
@@ -371,6 +385,7 @@ hipError_t force_integrate_pass(md_ctx* c, const State& s, int lpa, const double
 hipError_t force_only_pass(md_ctx* c, const State& s, const double4* pos) {
   if (c->multi) return launch_multi_force_only(c->L, c->g, s, c->mt, c->lpa, pos);
   if (c->half) return launch_half_force_only(c->L, c->g, s, c->t, pos);
+  if (c->lpa == 0) return launch_force_only_dyn(c->L, c->g, s, c->t, c->p.precision, pos);
   return launch_force_only(c->L, c->g, s, c->t, c->p.precision, c->lpa, pos);
 }
 
@@ -694,6 +709,15 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
     a0 += reps[r].n;
     c0 += d.ncell;
   }
+  // the re-sort's cell order: each replica's cells in bricks
+  std::vector<int32_t> corder((size_t)ls.cells);
+  for (int r = 0; r < n_rep; ++r) {
+    const RepDev& d = rd[r];
+    for (int32_t q = 0; q < d.ncell; ++q) {
+      const int32_t cx = q % d.nc[0], cy = (q / d.nc[0]) % d.nc[1], cz = q / (d.nc[0] * d.nc[1]);
+      corder[(size_t)d.cell0 + brick_position(cx, cy, cz, d.nc)] = d.cell0 + q;
+    }
+  }
   std::vector<AtomTile> atx = xcd_order(at, AtomTile{0, 0, 0, 0});
   std::vector<CellTile> ctx = xcd_order(ct, CellTile{0, -1});
 
@@ -715,6 +739,7 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   UP(b.reps, rd);
   UP(b.atiles, atx);
   UP(b.ctiles, ctx);
+  UP(b.cell_order, corder);
   UP(b.rho_val, rv);
   UP(b.phi_val, pv);
   UP(b.dpair3, d3);
@@ -835,6 +860,7 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   base.bin_idx = b.bin_idx;
   base.cell_start = b.cell_start;
   base.cell_stat = b.cell_stat;
+  base.cell_order = b.cell_order;
   base.status = b.status;
   base.rflag = b.rflag;
   base.sort_pos = b.sort_pos;
@@ -891,6 +917,9 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   c->pos_buf[1] = b.pos1;
   c->snap_pos = b.snap_pos;
   c->snap_vel = b.snap_vel;
+  c->ptile_buf = b.ptiles;
+  c->g.ptiles = b.ptiles;
+  c->g.n_ptiles = 0;
   c->energy_dev = b.energy;
   c->status = b.status;
   *out = c;
@@ -1237,70 +1266,160 @@ md_status md_set_schedule(md_ctx* c, int32_t lanes_per_atom) {
     if (s != MD_OK) return s;
   }
   c->lpa = l;
+  c->rep_lpa.clear();
   return MD_OK;
 }
 
-md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us) {
-  if (!c || reps < 1) return MD_E_ARG;
-  if (!c->built) return MD_E_ORDER;
+md_status md_set_replica_schedule(md_ctx* c, const int32_t* lanes) {
+  if (!c || !lanes) return MD_E_ARG;
+  for (int r = 0; r < c->n_rep; ++r)
+    if (!(lanes[r] == 1 || lanes[r] == 2 || lanes[r] == 4 || lanes[r] == 8)) return MD_E_ARG;
+  bool same = true;
+  for (int r = 1; r < c->n_rep; ++r) same = same && lanes[r] == lanes[0];
+  // one value for all, or a form whose passes walk atom tiles only: the uniform kernels
+  if (same) return md_set_schedule(c, lanes[0]);
+  if (c->half || c->multi || c->p.launch_mode == MD_LAUNCH_PERSISTENT) return MD_E_ARG;
+  // pair tiles: replica r in tiles of 64 / lanes[r] atoms, in replica order, then
+  // each XCD's contiguous share at positions xcd, xcd + 8, ...
+  std::vector<PairTile> pt;
+  int64_t a0 = 0;
+  for (int r = 0; r < c->n_rep; ++r) {
+    const int64_t per = 64 / lanes[r];
+    for (int64_t t0 = 0; t0 < c->reps[r].n; t0 += per)
+      pt.push_back(PairTile{r, (int32_t)(a0 + t0), (int32_t)std::min<int64_t>(per, c->reps[r].n - t0),
+                            lanes[r]});
+    a0 += c->reps[r].n;
+  }
+  std::vector<PairTile> ptx = xcd_order(pt, PairTile{0, 0, 0, 1});
+  md_status s = drop_graphs(c);
+  if (s != MD_OK) return s;
+  HIPC(c, hipStreamSynchronize(c->L.stream));
+  HIPC(c, hipMemcpy(c->ptile_buf, ptx.data(), ptx.size() * sizeof(PairTile),
+                    hipMemcpyHostToDevice));
+  c->g.n_ptiles = (int64_t)ptx.size();
+  c->rep_lpa.assign(lanes, lanes + c->n_rep);
+  c->lpa = 0;
+  return MD_OK;
+}
+
+md_status md_get_replica_schedule(md_ctx* c, int32_t* lanes) {
+  if (!c || !lanes) return MD_E_ARG;
+  for (int r = 0; r < c->n_rep; ++r) lanes[r] = c->rep_lpa.empty() ? c->lpa : c->rep_lpa[r];
+  return MD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Microseconds per round of the step's density and force+integrate kernels
+// under the schedule `lpa` (a uniform value, or 0 for the pair-tile table):
+// one untimed round, then reps timed rounds (events on the context stream).
+// The rebuild flags written go to scratch words; the caller restores the state.
+md_status time_rounds(md_ctx* c, int lpa, int reps, hipEvent_t e0, hipEvent_t e1, float* us) {
   State& s = c->st[c->cur];
-  hipEvent_t e0, e1;
-  HIPC(c, hipEventCreate(&e0));
-  HIPC(c, hipEventCreate(&e1));
+  for (int r = 0; r <= reps; ++r) {
+    if (r == 1) HIPC(c, hipEventRecord(e0, c->L.stream));
+    HIPC(c, density_pass(c, s, lpa, s.pos, nullptr, nullptr, nullptr, false));
+    HIPC(c, force_integrate_pass(c, s, lpa, s.pos, c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
+                                 s.rflag + 2 * c->n_rep));
+  }
+  float ms = 0.f;
+  HIPC(c, hipEventRecord(e1, c->L.stream));
+  HIPC(c, hipEventSynchronize(e1));
+  HIPC(c, hipEventElapsedTime(&ms, e0, e1));
+  *us = 1000.f * ms / (float)reps;
+  return MD_OK;
+}
+
+// Replica size class of the per-replica search: up to 2,048 atoms, up to
+// 8,192, larger.
+int size_class(int64_t n) { return n <= 2048 ? 0 : (n <= 8192 ? 1 : 2); }
+
+md_status autotune_impl(md_ctx* c, int32_t reps, hipEvent_t e0, hipEvent_t e1, int* best_lpa,
+                        float* best_us) {
   const int cand[4] = {1, 2, 4, 8};
   // the half-list passes run one lane per atom: time that one schedule
   const int n_cand = c->half ? 1 : 4;
   float per[4] = {3.4e38f, 3.4e38f, 3.4e38f, 3.4e38f};
-  md_status rc = MD_OK;
-  // the step's own kernels (density, then forces with the integration) on the
-  // current state; velocities and positions come back from a snapshot after
-  // the sweeps, and the rebuild flags written go to scratch words
-  HIPC(c, launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, false));
-  // two sweeps over the candidates, keeping each one's faster sweep
-  for (int sweep = 0; sweep < 2 && rc == MD_OK; ++sweep) {
-    for (int q = 0; q < n_cand && rc == MD_OK; ++q) {
-      const int l = cand[q];
-      // one untimed round, then reps timed rounds
-      for (int r = 0; r <= reps && rc == MD_OK; ++r) {
-        if (r == 1) {
-          hipError_t e = hipEventRecord(e0, c->L.stream);
-          if (e != hipSuccess) rc = hip_fail(c, e, "hipEventRecord");
-        }
-        hipError_t e = density_pass(c, s, l, s.pos, nullptr, nullptr, nullptr, false);
-        if (e == hipSuccess)
-          e = force_integrate_pass(c, s, l, s.pos, c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
-                                   s.rflag + 2 * c->n_rep);
-        if (e != hipSuccess) rc = hip_fail(c, e, "autotune launch");
-      }
-      if (rc != MD_OK) break;
-      float ms = 0.f;
-      hipError_t e = hipEventRecord(e1, c->L.stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        rc = hip_fail(c, e, "autotune timing");
-        break;
-      }
-      per[q] = std::min(per[q], 1000.f * ms / (float)reps);
+  md_status rc;
+  // two sweeps over the uniform candidates, keeping each one's faster sweep
+  for (int sweep = 0; sweep < 2; ++sweep)
+    for (int q = 0; q < n_cand; ++q) {
+      float us = 0.f;
+      if ((rc = time_rounds(c, cand[q], reps, e0, e1, &us)) != MD_OK) return rc;
+      per[q] = std::min(per[q], us);
     }
-  }
-  if (rc == MD_OK) {
-    hipError_t e = launch_snapshot(c->L, c->g, s, c->snap_pos, c->snap_vel, true);
-    if (e != hipSuccess) rc = hip_fail(c, e, "autotune restore");
-  }
   float best = 3.4e38f;
-  int pick = c->lpa;
+  int pick = c->lpa > 0 ? c->lpa : 1;
   for (int q = 0; q < n_cand; ++q)
     if (per[q] < best) {
       best = per[q];
       pick = cand[q];
     }
+  *best_lpa = pick;
+  *best_us = best;
+  if ((rc = md_set_schedule(c, pick)) != MD_OK) return rc;
+  if (c->n_rep < 2 || c->half || c->multi || c->p.launch_mode == MD_LAUNCH_PERSISTENT)
+    return MD_OK;
+  // batched replicas: one lanes-per-atom value per size class, found class by
+  // class from the uniform choice (two passes), kept if it beats that choice
+  std::vector<int32_t> lanes(c->n_rep, pick);
+  bool present[3] = {false, false, false};
+  for (int r = 0; r < c->n_rep; ++r) present[size_class(c->reps[r].n)] = true;
+  float cur_best = best;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int k = 0; k < 3; ++k) {
+      if (!present[k]) continue;
+      int keep = -1;
+      for (int q = 0; q < 4; ++q) {
+        std::vector<int32_t> trial = lanes;
+        for (int r = 0; r < c->n_rep; ++r)
+          if (size_class(c->reps[r].n) == k) trial[r] = cand[q];
+        if ((rc = md_set_replica_schedule(c, trial.data())) != MD_OK) return rc;
+        float us = 0.f;
+        if ((rc = time_rounds(c, c->lpa, reps, e0, e1, &us)) != MD_OK) return rc;
+        if (us < cur_best) {
+          cur_best = us;
+          keep = cand[q];
+        }
+      }
+      if (keep > 0)
+        for (int r = 0; r < c->n_rep; ++r)
+          if (size_class(c->reps[r].n) == k) lanes[r] = keep;
+    }
+  if (cur_best < best) {
+    *best_us = cur_best;
+    return md_set_replica_schedule(c, lanes.data());
+  }
+  return md_set_schedule(c, pick);
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_autotune(md_ctx* c, int32_t reps, int32_t* best_lpa, float* best_us) {
+  if (!c || reps < 1) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  hipEvent_t e0, e1;
+  HIPC(c, hipEventCreate(&e0));
+  HIPC(c, hipEventCreate(&e1));
+  // velocities and positions come back from a snapshot after the sweeps
+  md_status rc = MD_OK;
+  hipError_t e = launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, false);
+  if (e != hipSuccess) rc = hip_fail(c, e, "autotune snapshot");
+  int pick = 0;
+  float best = 0.f;
+  if (rc == MD_OK) rc = autotune_impl(c, reps, e0, e1, &pick, &best);
+  e = launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, true);
+  if (rc == MD_OK && e != hipSuccess) rc = hip_fail(c, e, "autotune restore");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != MD_OK) return rc;
   if (best_lpa) *best_lpa = pick;
   if (best_us) *best_us = best;
-  return md_set_schedule(c, pick);
+  return MD_OK;
 }
 
 void md_destroy(md_ctx* c) {
@@ -1310,3 +1429,4 @@ void md_destroy(md_ctx* c) {
 }
 
 }  // extern "C"
+

@@ -57,8 +57,8 @@ __global__ __launch_bounds__(kHalfThreads) void k_half_density(
   const int last = t.nr - 2;
   const TileWalk w = tile_walk<1>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     if (w.a >= tl.count) continue;
     const RepDev& rp = g.reps[tl.rep];
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(kHalfThreads) void k_half_force(Geometry g, State s
   const int last = t.nr - 2;
   const TileWalk w = tile_walk<1>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     if (w.a >= tl.count) continue;
     const RepDev& rp = g.reps[tl.rep];

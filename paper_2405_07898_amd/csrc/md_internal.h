@@ -73,6 +73,15 @@ struct AtomTile {
   int32_t pad;
 };
 
+// Work unit of the pair passes under a per-replica schedule: one wave takes
+// `count` (<= 64 / lpa) atoms from `begin`, with lpa lanes on each atom.
+struct PairTile {
+  int32_t rep;
+  int32_t begin;
+  int32_t count;
+  int32_t lpa;
+};
+
 struct CellTile {
   int32_t rep;
   int32_t cell;  // cell index within the replica (-1 = idle block)
@@ -99,6 +108,8 @@ struct Geometry {
   const RepDev* reps;
   const AtomTile* atiles;
   const CellTile* ctiles;
+  const PairTile* ptiles;  // per-replica schedule (null: one lanes-per-atom value)
+  int64_t n_ptiles;        // a multiple of the XCD count
   int64_t n;        // total atoms (ELL stride)
   int32_t n_atiles;
   int32_t n_ctiles;
@@ -131,6 +142,8 @@ struct State {
   int32_t* bin_idx;  // [total cells][cell_cap]
   int32_t* cell_start;  // [total cells + 1]
   int32_t* cell_stat;   // [total cells][3]: longest list, list entries, atoms (last build)
+  const int32_t* cell_order;  // [total cells]: the cell whose atoms the re-sort places
+                              // at each position (brick order within each replica)
   int32_t* status;   // SW_WORDS
   int32_t* rflag;    // [3][n_rep]: per-replica rebuild requests (parity 0, 1, scratch)
   double4* sort_pos;
@@ -175,6 +188,24 @@ struct MultiTables {
   int32_t lds_pad;
 };
 
+// The re-sort by cell lays the cells of a replica out in bricks of
+// kSortBrick^3 cells (bricks in row-major order, the cells of a brick
+// row-major), so that a run of consecutive atoms fills a compact block of
+// space rather than a row.  Position of cell (cx, cy, cz) in that order, for
+// a grid of n[0] x n[1] x n[2] cells (edge bricks are cut to the grid).
+constexpr int kSortBrick = 4;
+
+__host__ __device__ inline int32_t brick_position(int32_t cx, int32_t cy, int32_t cz,
+                                                  const int32_t* n) {
+  const int32_t B = kSortBrick;
+  const int32_t bx = cx / B, by = cy / B, bz = cz / B;
+  const int32_t lx = cx - bx * B, ly = cy - by * B, lz = cz - bz * B;
+  const int32_t sx = n[0] - bx * B < B ? n[0] - bx * B : B;
+  const int32_t sy = n[1] - by * B < B ? n[1] - by * B : B;
+  const int32_t sz = n[2] - bz * B < B ? n[2] - bz * B : B;
+  return bz * B * n[1] * n[0] + sz * by * B * n[0] + sz * sy * bx * B + (lz * sy + ly) * sx + lx;
+}
+
 // ---------------------------------------------------------------- launchers
 
 struct Launch {
@@ -202,6 +233,17 @@ hipError_t launch_force_integrate(const Launch& L, const Geometry& g, const Stat
                                   double4* pos_out, int32_t* flag_next, int32_t* rflag_next);
 hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                              int precision, int lpa, const double4* pos);
+// The same three passes under a per-replica schedule (g.ptiles): each wave
+// takes one pair tile and works on it with that tile's lanes per atom.
+hipError_t launch_density_dyn(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                              int precision, const double4* pos, const int32_t* cond_zero,
+                              int32_t* clear_flag, int32_t* rclear, int64_t n_cells_total,
+                              bool want_rho);
+hipError_t launch_force_integrate_dyn(const Launch& L, const Geometry& g, const State& s,
+                                      const Tables& t, int precision, const double4* pos_in,
+                                      double4* pos_out, int32_t* flag_next, int32_t* rflag_next);
+hipError_t launch_force_only_dyn(const Launch& L, const Geometry& g, const State& s,
+                                 const Tables& t, int precision, const double4* pos);
 size_t density_lds_bytes(const Tables& t, int precision);
 size_t force_lds_bytes(const Tables& t, int precision);
 hipError_t allow_pair_lds(const Tables& t, int precision);

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(64) void k_import(Geometry g, State s, const double
       wrap_pos(make_double4(x[3 * i + 0], x[3 * i + 1], x[3 * i + 2], 0.0), rp, bad);
   if (bad) set_bits(s.status, ST_LOST);
   s.pos[i] = p;
-  s.vel[i] = make_double4(v[3 * i + 0], v[3 * i + 1], v[3 * i + 2], 0.0);
+  s.vel[i] = v ? make_double4(v[3 * i + 0], v[3 * i + 1], v[3 * i + 2], 0.0)
+               : make_double4(0.0, 0.0, 0.0, 0.0);
   s.id[i] = (int32_t)i;
   if (s.type) s.type[i] = s.type_orig[i];
 }
@@ -482,16 +483,19 @@ __global__ __launch_bounds__(1024) void k_cell_stats(State s, int64_t m) {
 
 // ============================================================ sort by cell
 
-// Exclusive scan of the (capped) bin counts over all cells, one block.
+// Exclusive scan of the (capped) bin counts over all cells taken in the
+// order `order` (position -> cell), one block: start[c] is where cell c's
+// atoms begin.
 __global__ __launch_bounds__(1024) void k_scan_cells(const int32_t* __restrict__ cnt,
-                                                     int32_t* __restrict__ start, int64_t m,
+                                                     int32_t* __restrict__ start,
+                                                     const int32_t* __restrict__ order, int64_t m,
                                                      int32_t cap) {
   __shared__ long long s_sum[1024];
   const int t = threadIdx.x;
   const int64_t per = (m + 1023) / 1024;
   const int64_t b = t * per, e = min(m, b + per);
   long long acc = 0;
-  for (int64_t k = b; k < e; ++k) acc += min(cnt[k], cap);
+  for (int64_t k = b; k < e; ++k) acc += min(cnt[order[k]], cap);
   s_sum[t] = acc;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -502,8 +506,9 @@ __global__ __launch_bounds__(1024) void k_scan_cells(const int32_t* __restrict__
   }
   long long run = s_sum[t] - acc;
   for (int64_t k = b; k < e; ++k) {
-    start[k] = (int32_t)run;
-    run += min(cnt[k], cap);
+    const int32_t c = order[k];
+    start[c] = (int32_t)run;
+    run += min(cnt[c], cap);
   }
   if (t == 1023) start[m] = (int32_t)s_sum[1023];
 }
@@ -686,8 +691,8 @@ __global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
   if (err) return;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];
@@ -841,8 +846,8 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];
@@ -878,8 +883,8 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry 
   if (err) return;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];
@@ -890,6 +895,126 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_only(Geometry 
     if (active && w.sub == 0) {
       s.frc[i] = make_double4(fx, fy, fz, 0.0);
       if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
+    }
+  }
+}
+
+// ============================================================ per-replica schedules
+
+// Batched replicas of very different sizes may each want their own lanes per
+// atom.  These kernels walk pair tiles instead of atom tiles: wave w of a
+// workgroup takes the workgroup's pair tiles w, w + W, w + 2W, ... (W waves),
+// and works on each with the tile's own lanes per atom (a wave-uniform
+// branch into the same device code as the uniform kernels, so a replica's
+// results depend only on its own lanes-per-atom value).
+
+template <int PREC, int LPA>
+__device__ __forceinline__ void density_tile(const Geometry& g, const State& s, const Tables& t,
+                                             double4* pos, const void* lds, const PairTile& tl,
+                                             int lane, int want_rho) {
+  const int a = lane / LPA, sub = lane % LPA;
+  const bool active = a < tl.count;
+  const int64_t i = tl.begin + (active ? a : 0);
+  const double rho_i = density_of<PREC, LPA>(g, s, t, g.reps[tl.rep], pos, lds, i, active, sub);
+  if (active && sub == 0) store_fprime<PREC>(s, t, pos, i, rho_i, want_rho);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(768) void k_density_dyn(Geometry g, State s, Tables t,
+                                                      double4* __restrict__ pos,
+                                                      const int32_t* cond_zero, int32_t* clear_flag,
+                                                      int32_t* rclear, int64_t ncells, int want_rho) {
+  extern __shared__ double4 lds_d4[];
+  const int32_t zero_bins = cond_zero ? *cond_zero : 0;
+  const bool err = has_error(s.status);
+  if (clear_flag && blockIdx.x == 0) {
+    if (threadIdx.x == 0) *clear_flag = 0;
+    for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rclear[r] = 0;
+  }
+  if (PREC == 0) lds_fill<4>(lds_d4, t.rho_val, t.nr - 1, lds_d4 + (t.nr - 1));
+  else
+    lds_fill<4>(reinterpret_cast<float4*>(lds_d4), t.rho_val32, t.nr - 1,
+                reinterpret_cast<float4*>(lds_d4) + (t.nr - 1));
+  if (zero_bins) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncells;
+         k += (int64_t)gridDim.x * blockDim.x)
+      s.bin_cnt[k] = 0;
+  }
+  __syncthreads();
+  if (err) return;
+  const int nw = (int)blockDim.x >> 6, wave = (int)threadIdx.x >> 6, lane = lane_id();
+  for (int64_t it = wave;; it += nw) {
+    const int64_t b = walk_tile(it, g.n_ptiles);
+    if (b < 0) break;
+    const PairTile tl = g.ptiles[b];
+    switch (tl.lpa) {
+      case 1: density_tile<PREC, 1>(g, s, t, pos, lds_d4, tl, lane, want_rho); break;
+      case 2: density_tile<PREC, 2>(g, s, t, pos, lds_d4, tl, lane, want_rho); break;
+      case 4: density_tile<PREC, 4>(g, s, t, pos, lds_d4, tl, lane, want_rho); break;
+      default: density_tile<PREC, 8>(g, s, t, pos, lds_d4, tl, lane, want_rho); break;
+    }
+  }
+}
+
+// Forces of one pair tile; with pos_out, the leap-frog update as in
+// k_force_integrate (returns whether this wave saw an atom move past skin/2),
+// else the forces into s.frc as in k_force_only.
+template <int PREC, int LPA>
+__device__ __forceinline__ bool force_tile(const Geometry& g, const State& s, const Tables& t,
+                                           const double4* __restrict__ pos_in,
+                                           double4* __restrict__ pos_out, const void* lds,
+                                           const PairTile& tl, int lane) {
+  const int a = lane / LPA, sub = lane % LPA;
+  const bool active = a < tl.count;
+  const int64_t i = tl.begin + (active ? a : 0);
+  const double4 pi = pos_in[i];
+  double4 v = make_double4(0.0, 0.0, 0.0, 0.0), xr = v;
+  if (pos_out && active && sub == 0) {
+    v = s.vel[i];
+    xr = s.xref[i];
+  }
+  double fx, fy, fz;
+  pair_forces<PREC, LPA>(g, s, t, g.reps[tl.rep], pos_in, lds, i, active, sub, pi, fx, fy, fz);
+  bool far = false;
+  if (active && sub == 0) {
+    if (pos_out) {
+      far = leapfrog(g, s, i, pi, v, xr, fx, fy, fz, pos_out);
+    } else {
+      s.frc[i] = make_double4(fx, fy, fz, 0.0);
+      if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
+    }
+  }
+  return __ballot(far) != 0ull;
+}
+
+// pos_out null: forces only (into s.frc); else force pass fused with the
+// leap-frog update, as k_force_integrate.
+template <int PREC>
+__global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_dyn(
+    Geometry g, State s, Tables t, const double4* __restrict__ pos_in,
+    double4* __restrict__ pos_out, int32_t* flag_next, int32_t* rflag_next) {
+  extern __shared__ double4 lds_d4[];
+  const bool err = has_error(s.status);
+  fill_force_table<PREC>(lds_d4, t);
+  __syncthreads();
+  if (err) return;
+  if (pos_out && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
+  const int nw = (int)blockDim.x >> 6, wave = (int)threadIdx.x >> 6, lane = lane_id();
+  for (int64_t it = wave;; it += nw) {
+    const int64_t b = walk_tile(it, g.n_ptiles);
+    if (b < 0) break;
+    const PairTile tl = g.ptiles[b];
+    bool far;
+    switch (tl.lpa) {
+      case 1: far = force_tile<PREC, 1>(g, s, t, pos_in, pos_out, lds_d4, tl, lane); break;
+      case 2: far = force_tile<PREC, 2>(g, s, t, pos_in, pos_out, lds_d4, tl, lane); break;
+      case 4: far = force_tile<PREC, 4>(g, s, t, pos_in, pos_out, lds_d4, tl, lane); break;
+      default: far = force_tile<PREC, 8>(g, s, t, pos_in, pos_out, lds_d4, tl, lane); break;
+    }
+    // one wave covers atoms of one pair tile, hence of one replica
+    if (far && lane == 0) {
+      *flag_next = 1;
+      rflag_next[tl.rep] = 1;
     }
   }
 }
@@ -1011,8 +1136,8 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
     {
       const TileWalk w = tile_walk<LPA>();
       for (int64_t it = w.q;; it += w.tpi) {
-        const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-        if (b >= g.n_atiles) break;
+        const int64_t b = walk_tile(it, g.n_atiles);
+        if (b < 0) break;
         const AtomTile tl = g.atiles[b];
         const bool active = w.a < tl.count;
         const RepDev& rp = g.reps[tl.rep];
@@ -1028,8 +1153,8 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
     {
       const TileWalk w = tile_walk<LPA>();
       for (int64_t it = w.q;; it += w.tpi) {
-        const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-        if (b >= g.n_atiles) break;
+        const int64_t b = walk_tile(it, g.n_atiles);
+        if (b < 0) break;
         const AtomTile tl = g.atiles[b];
         const bool active = w.a < tl.count;
         const RepDev& rp = g.reps[tl.rep];
@@ -1232,8 +1357,8 @@ hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64
   hipError_t e;
   if ((e = launch_zero_bins(L, s, m)) != hipSuccess) return e;
   if ((e = launch_bin(L, g, s, nullptr, nullptr)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, L.stream, s.bin_cnt, s.cell_start, m,
-                     g.cell_cap);
+  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, L.stream, s.bin_cnt, s.cell_start,
+                     s.cell_order, m, g.cell_cap);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, L.stream, s,
                      m, g.cell_cap);
@@ -1327,6 +1452,40 @@ hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s,
 #undef MDK_O
 }
 
+hipError_t launch_density_dyn(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                              int precision, const double4* pos, const int32_t* cond_zero,
+                              int32_t* clear_flag, int32_t* rclear, int64_t n_cells_total,
+                              bool want_rho) {
+  double4* p = const_cast<double4*>(pos);
+  const int w = want_rho ? 1 : 0;
+  if (precision == 0)
+    hipLaunchKernelGGL(k_density_dyn<0>, dim3(2 * L.persist_blocks), dim3(768),
+                       density_lds_bytes(t, 0), L.stream, g, s, t, p, cond_zero, clear_flag,
+                       rclear, n_cells_total, w);
+  else
+    hipLaunchKernelGGL(k_density_dyn<1>, dim3(2 * L.persist_blocks), dim3(768),
+                       density_lds_bytes(t, 1), L.stream, g, s, t, p, cond_zero, clear_flag,
+                       rclear, n_cells_total, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_integrate_dyn(const Launch& L, const Geometry& g, const State& s,
+                                      const Tables& t, int precision, const double4* pos_in,
+                                      double4* pos_out, int32_t* flag_next, int32_t* rflag_next) {
+  if (precision == 0)
+    hipLaunchKernelGGL(k_force_dyn<0>, dim3(L.persist_blocks), dim3(768), force_lds_bytes(t, 0),
+                       L.stream, g, s, t, pos_in, pos_out, flag_next, rflag_next);
+  else
+    hipLaunchKernelGGL(k_force_dyn<1>, dim3(L.persist_blocks), dim3(1024), force_lds_bytes(t, 1),
+                       L.stream, g, s, t, pos_in, pos_out, flag_next, rflag_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_only_dyn(const Launch& L, const Geometry& g, const State& s,
+                                 const Tables& t, int precision, const double4* pos) {
+  return launch_force_integrate_dyn(L, g, s, t, precision, pos, nullptr, nullptr, nullptr);
+}
+
 // The persistent step kernel: the force table (as in the force pass) and one
 // build staging area per wave.
 size_t persist_lds_bytes(const Tables& t, int prec, int cell_cap) {
@@ -1394,6 +1553,16 @@ static hipError_t allow_lds_one(size_t dens, size_t force) {
 hipError_t allow_pair_lds(const Tables& t, int precision) {
   const size_t d = density_lds_bytes(t, precision), f = force_lds_bytes(t, precision);
   hipError_t e;
+  const void* dk = precision == 0 ? reinterpret_cast<const void*>(&k_density_dyn<0>)
+                                  : reinterpret_cast<const void*>(&k_density_dyn<1>);
+  const void* fk = precision == 0 ? reinterpret_cast<const void*>(&k_force_dyn<0>)
+                                  : reinterpret_cast<const void*>(&k_force_dyn<1>);
+  if ((e = hipFuncSetAttribute(dk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)d)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)f)) !=
+      hipSuccess)
+    return e;
   if (precision == 0) {
     if ((e = allow_lds_one<0, 1>(d, f)) != hipSuccess) return e;
     if ((e = allow_lds_one<0, 2>(d, f)) != hipSuccess) return e;

@@ -70,8 +70,8 @@ __global__ __launch_bounds__(kMultiThreads) void k_density_multi(
   const int last = t.nr - 2;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];
@@ -238,8 +238,8 @@ __global__ __launch_bounds__(kMultiForceThreads) void k_force_integrate_multi(
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_STEPS) += 1ull;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];
@@ -291,8 +291,8 @@ __global__ __launch_bounds__(kMultiForceThreads) void k_force_only_multi(Geometr
   if (err) return;
   const TileWalk w = tile_walk<LPA>();
   for (int64_t it = w.q;; it += w.tpi) {
-    const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-    if (b >= g.n_atiles) break;
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
     const AtomTile tl = g.atiles[b];
     const bool active = w.a < tl.count;
     const RepDev& rp = g.reps[tl.rep];

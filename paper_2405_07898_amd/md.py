@@ -58,7 +58,8 @@ _lib = None
 EXPORTED = [
     "md_workspace_size", "md_workspace_bytes", "md_init", "md_init_batch", "md_create", "md_set_state", "md_build_neighbors", "md_step",
     "md_energy", "md_get_state", "md_compute_forces", "md_stats", "md_get_cells",
-    "md_get_neighbors", "md_launch_pass", "md_set_schedule", "md_autotune", "md_last_error",
+    "md_get_neighbors", "md_launch_pass", "md_set_schedule", "md_set_replica_schedule",
+    "md_get_replica_schedule", "md_autotune", "md_last_error",
     "md_status_string", "md_destroy", "md_create_multi", "md_set_types",
     "md_fm_workspace_size", "md_fm_create", "md_fm_forward", "md_fm_backward", "md_fm_destroy",
 ]
@@ -96,6 +97,8 @@ def lib():
             "md_get_neighbors": (i32, [vp, vp, vp, i32]),
             "md_launch_pass": (i32, [vp, i32, i32]),
             "md_set_schedule": (i32, [vp, i32]),
+            "md_set_replica_schedule": (i32, [vp, P(i32)]),
+            "md_get_replica_schedule": (i32, [vp, P(i32)]),
             "md_autotune": (i32, [vp, i32, P(i32), P(C.c_float)]),
             "md_last_error": (C.c_char_p, [vp]),
             "md_status_string": (C.c_char_p, [i32]),
@@ -312,6 +315,19 @@ class System:
     def set_schedule(self, lanes_per_atom: int):
         return _check(lib().md_set_schedule(self.ctx, int(lanes_per_atom)), "md_set_schedule",
                       self.ctx)
+
+    def set_replica_schedule(self, lanes):
+        """Lanes per atom of each replica (n_rep values of 1, 2, 4 or 8)."""
+        a = np.ascontiguousarray(lanes, dtype=np.int32)
+        assert a.shape == (self.n_rep,)
+        return _check(lib().md_set_replica_schedule(self.ctx, a.ctypes.data_as(C.POINTER(C.c_int32))),
+                      "md_set_replica_schedule", self.ctx)
+
+    def replica_schedule(self):
+        a = np.zeros(self.n_rep, dtype=np.int32)
+        _check(lib().md_get_replica_schedule(self.ctx, a.ctypes.data_as(C.POINTER(C.c_int32))),
+               "md_get_replica_schedule", self.ctx)
+        return a
 
     def autotune(self, reps: int = 20):
         lpa = C.c_int32()

@@ -132,16 +132,20 @@ def test_init_build_step_energy_against_oracle(md, tabs, oracle_lib, n_rep):
         assert abs(ke[r] - e_ke) <= 1e-9 * abs(e_ke), (r, ke[r], e_ke)
 
 
-def test_step_calls_of_any_length_equal_one_call(md, tabs):
+def test_step_calls_of_any_length_equal_one_call(md, tabs, oracle_lib):
     """Step calls of lengths that fill no chunk, leave the odd position buffer
     current or evict kept graphs run the same kernels in the same order as
-    one call: bitwise the same state."""
+    one call: bitwise the same state when no re-sort by cell falls between
+    chunks.  With a re-sort after every chunk (whose place depends on how the
+    steps are split into calls, and which reorders each atom's list) the run
+    still follows the oracle."""
     box = configs.small_box(7, seed=85, temperature=2500.0, sigma_x=0.05)
-    lens = [7, 13, 1, 19, 2, 40, 5, 3, 11, 20, 9, 6, 1]
+    lens = [7, 13, 1, 19, 2, 20, 5, 3, 11, 9, 6, 1]
     _say(f"[gpu] step lengths {lens} (chunk 20), n={box.n}")
 
-    def run(calls):
-        s = md.System(_params(md, chunk_steps=20), tabs, [box.n], box.box[None, :])
+    def run(calls, sort_every):
+        s = md.System(_params(md, chunk_steps=20, sort_every=sort_every), tabs, [box.n],
+                      box.box[None, :])
         s.set_state(box.x, box.v)
         s.build_neighbors()
         for n in calls:
@@ -151,30 +155,38 @@ def test_step_calls_of_any_length_equal_one_call(md, tabs):
         s.close()
         return x, v, f, st
 
-    xa, va, fa, sa = run(lens)
-    xb, vb, fb, sb = run([sum(lens)])
+    xa, va, fa, sa = run(lens, 0)
+    xb, vb, fb, sb = run([sum(lens)], 0)
     assert sa["steps"] == sb["steps"] == sum(lens)
     assert sa["rebuilds"] == sb["rebuilds"] >= 2
     assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(fa, fb)
+    xc, vc, _, sc = run(lens, 1)
+    assert sc["steps"] == sum(lens)
+    _close(xc, vc, box, _oracle_run(oracle_lib, tabs, box, sum(lens)))
 
 
 def test_cell_overflow_at_a_resort_rolls_back_cleanly(md, tabs, oracle_lib):
-    """A hot 432-atom box whose fullest cell grows from 20 to 21 atoms (steps
-    27-68 of the oracle run), cell capacity 20 and a re-sort at every 10-step
-    chunk: md_step reports MD_E_CELL_OVERFLOW and leaves the last clean
-    snapshot, every atom at its own id, equal to the oracle at that step."""
-    box = configs.small_box(6, seed=71, temperature=3000.0, sigma_x=0.05)
+    """A 1,458-atom box at 4,000 K with a 2 A skin (no list rebuild falls due
+    inside a 10-step chunk) and a re-sort by cell before every chunk.  Its
+    fullest 7.4 A cell holds 28, 29, 29 and then 30 atoms at steps 0, 10, 20
+    and 30 of the oracle run, so with a cell capacity of 29 the binning of the
+    re-sort at step 30 overflows: md_step reports MD_E_CELL_OVERFLOW, the
+    re-sort moves nothing, and the state rolls back to the snapshot of step
+    20, every atom at its own id, equal to the oracle there."""
+    box = configs.small_box(9, seed=72, temperature=4000.0, sigma_x=0.05)
+    skin = 2.0
     _say(f"[gpu] cell overflow at a re-sort, n={box.n}")
-    s = md.System(_params(md, chunk_steps=10, sort_every=1, cell_capacity=20), tabs, [box.n],
-                  box.box[None, :])
+    s = md.System(_params(md, chunk_steps=10, sort_every=1, cell_capacity=29, skin=skin,
+                          nbr_capacity=256), tabs, [box.n], box.box[None, :])
     s.set_state(box.x, box.v)
     s.build_neighbors()
     rc = s.step(100, check=False)
     assert rc == md.MD_E_CELL_OVERFLOW, rc
     st = s.stats()
-    k = int(st["steps"])
-    assert 0 < k < 100 and k % 10 == 0, k
+    assert st["steps"] == 20 and st["rebuilds"] == 0, st
     x, v, _ = s.get_state(want_f=False)
     s.close()
-    out = _oracle_run(oracle_lib, tabs, box, k)
+    out = oracle_lib.md_run(box.x, box.v, box.box, tabs, 20, mass=configs.MASS, dt=configs.DT,
+                            r_cut=RC, skin=skin, ftm2v=configs.FTM2V, cap=256)
+    assert out["code"] == 0
     _close(x.cpu().numpy(), v.cpu().numpy(), box, out)
