@@ -67,7 +67,7 @@ def force_pass_bytes(n_atoms: int, n_l: float, mixed: bool) -> float:
     (fused away): 132 + 4 n_l (mixed 128 + 4 n_l).  Neighbour gathers are
     cache-served and not counted.
     """
-    per = 24 + (4 if mixed else 8) + 4 + 4 * n_l + 48 + 24
+    per = 24 + (4 if mixed else 8) + 4 + 4 * n_l + 48 + 24 + 24
     return n_atoms * per
 
 

@@ -192,7 +192,7 @@ struct Buffers {
   double *rho, *epair;
   int32_t *id, *cell_of, *cnt;
   uint32_t* nbr;
-  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *cell_order, *status, *rflag;
+  int32_t *bin_cnt, *bin_idx, *cell_start, *cell_stat, *status, *rflag;
   double4 *sort_pos, *sort_vel;
   int32_t* sort_id;
   double4 *snap_pos, *snap_vel;
@@ -254,7 +254,6 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.bin_idx = c.take<int32_t>((size_t)s.cells * p->cell_capacity);
   o.cell_start = c.take<int32_t>((size_t)s.cells + 1);
   o.cell_stat = c.take<int32_t>(3 * (size_t)s.cells);
-  o.cell_order = c.take<int32_t>((size_t)s.cells);
   o.status = c.take<int32_t>(SW_WORDS);
   o.rflag = c.take<int32_t>(3 * (size_t)n_rep);
   o.sort_pos = c.take<double4>(N);
@@ -709,15 +708,6 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
     a0 += reps[r].n;
     c0 += d.ncell;
   }
-  // the re-sort's cell order: each replica's cells in bricks
-  std::vector<int32_t> corder((size_t)ls.cells);
-  for (int r = 0; r < n_rep; ++r) {
-    const RepDev& d = rd[r];
-    for (int32_t q = 0; q < d.ncell; ++q) {
-      const int32_t cx = q % d.nc[0], cy = (q / d.nc[0]) % d.nc[1], cz = q / (d.nc[0] * d.nc[1]);
-      corder[(size_t)d.cell0 + brick_position(cx, cy, cz, d.nc)] = d.cell0 + q;
-    }
-  }
   std::vector<AtomTile> atx = xcd_order(at, AtomTile{0, 0, 0, 0});
   std::vector<CellTile> ctx = xcd_order(ct, CellTile{0, -1});
 
@@ -739,7 +729,6 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   UP(b.reps, rd);
   UP(b.atiles, atx);
   UP(b.ctiles, ctx);
-  UP(b.cell_order, corder);
   UP(b.rho_val, rv);
   UP(b.phi_val, pv);
   UP(b.dpair3, d3);
@@ -860,7 +849,6 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   base.bin_idx = b.bin_idx;
   base.cell_start = b.cell_start;
   base.cell_stat = b.cell_stat;
-  base.cell_order = b.cell_order;
   base.status = b.status;
   base.rflag = b.rflag;
   base.sort_pos = b.sort_pos;

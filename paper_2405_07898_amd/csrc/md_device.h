@@ -93,25 +93,14 @@ struct TileWalk {
 };
 
 // Table position of the it-th atom tile (it = 0, 1, ...) a workgroup of a
-// pair pass takes, or -1 when it has none left.  The grid is a multiple of
-// the XCD count and so is the tile table, whose positions b, b + 8, b + 16, ...
-// hold consecutive tiles of XCD b % 8's contiguous share of the atoms.  With
-// kContiguousTiles each workgroup takes a contiguous run of its XCD's tiles,
-// so the tiles its waves work on at one time are neighbours in space and
-// share neighbour records in the CU's L1; otherwise workgroup w takes the
-// positions w, w + G, w + 2G, ... (tiles G/8 apart).
-constexpr bool kContiguousTiles = true;
-
-__device__ __forceinline__ int64_t walk_tile(int64_t it, int64_t n_atiles) {
-  if (kContiguousTiles) {
-    const int64_t per = n_atiles / kXcd, gx = (int64_t)gridDim.x / kXcd;
-    const int64_t m = (per + gx - 1) / gx;
-    const int64_t r = (int64_t)(blockIdx.x / kXcd) * m + it;
-    if (it >= m || r >= per) return -1;
-    return r * kXcd + (int64_t)(blockIdx.x % kXcd);
-  }
+// pair pass takes, or -1 when it has none left: workgroup w takes positions
+// w, w + G, w + 2G, ... (G = grid size, a multiple of the XCD count), so every
+// tile it takes is one the tile table placed on its own XCD.  (Giving each
+// workgroup a contiguous run of its XCD's tiles instead, so that the tiles in
+// flight on a CU are neighbours in space, was measured slower.)
+__device__ __forceinline__ int64_t walk_tile(int64_t it, int64_t n_tiles) {
   const int64_t b = blockIdx.x + (int64_t)gridDim.x * it;
-  return b < n_atiles ? b : -1;
+  return b < n_tiles ? b : -1;
 }
 
 template <int LPA>

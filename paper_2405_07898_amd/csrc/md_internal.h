@@ -142,8 +142,6 @@ struct State {
   int32_t* bin_idx;  // [total cells][cell_cap]
   int32_t* cell_start;  // [total cells + 1]
   int32_t* cell_stat;   // [total cells][3]: longest list, list entries, atoms (last build)
-  const int32_t* cell_order;  // [total cells]: the cell whose atoms the re-sort places
-                              // at each position (brick order within each replica)
   int32_t* status;   // SW_WORDS
   int32_t* rflag;    // [3][n_rep]: per-replica rebuild requests (parity 0, 1, scratch)
   double4* sort_pos;
@@ -187,24 +185,6 @@ struct MultiTables {
   int32_t lds_seg0;        // first segment of frow held in the force pass's LDS
   int32_t lds_pad;
 };
-
-// The re-sort by cell lays the cells of a replica out in bricks of
-// kSortBrick^3 cells (bricks in row-major order, the cells of a brick
-// row-major), so that a run of consecutive atoms fills a compact block of
-// space rather than a row.  Position of cell (cx, cy, cz) in that order, for
-// a grid of n[0] x n[1] x n[2] cells (edge bricks are cut to the grid).
-constexpr int kSortBrick = 4;
-
-__host__ __device__ inline int32_t brick_position(int32_t cx, int32_t cy, int32_t cz,
-                                                  const int32_t* n) {
-  const int32_t B = kSortBrick;
-  const int32_t bx = cx / B, by = cy / B, bz = cz / B;
-  const int32_t lx = cx - bx * B, ly = cy - by * B, lz = cz - bz * B;
-  const int32_t sx = n[0] - bx * B < B ? n[0] - bx * B : B;
-  const int32_t sy = n[1] - by * B < B ? n[1] - by * B : B;
-  const int32_t sz = n[2] - bz * B < B ? n[2] - bz * B : B;
-  return bz * B * n[1] * n[0] + sz * by * B * n[0] + sz * sy * bx * B + (lz * sy + ly) * sx + lx;
-}
 
 // ---------------------------------------------------------------- launchers
 

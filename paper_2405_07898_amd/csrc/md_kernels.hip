@@ -483,19 +483,16 @@ __global__ __launch_bounds__(1024) void k_cell_stats(State s, int64_t m) {
 
 // ============================================================ sort by cell
 
-// Exclusive scan of the (capped) bin counts over all cells taken in the
-// order `order` (position -> cell), one block: start[c] is where cell c's
-// atoms begin.
+// Exclusive scan of the (capped) bin counts over all cells, one block.
 __global__ __launch_bounds__(1024) void k_scan_cells(const int32_t* __restrict__ cnt,
-                                                     int32_t* __restrict__ start,
-                                                     const int32_t* __restrict__ order, int64_t m,
+                                                     int32_t* __restrict__ start, int64_t m,
                                                      int32_t cap) {
   __shared__ long long s_sum[1024];
   const int t = threadIdx.x;
   const int64_t per = (m + 1023) / 1024;
   const int64_t b = t * per, e = min(m, b + per);
   long long acc = 0;
-  for (int64_t k = b; k < e; ++k) acc += min(cnt[order[k]], cap);
+  for (int64_t k = b; k < e; ++k) acc += min(cnt[k], cap);
   s_sum[t] = acc;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -506,9 +503,8 @@ __global__ __launch_bounds__(1024) void k_scan_cells(const int32_t* __restrict__
   }
   long long run = s_sum[t] - acc;
   for (int64_t k = b; k < e; ++k) {
-    const int32_t c = order[k];
-    start[c] = (int32_t)run;
-    run += min(cnt[c], cap);
+    start[k] = (int32_t)run;
+    run += min(cnt[k], cap);
   }
   if (t == 1023) start[m] = (int32_t)s_sum[1023];
 }
@@ -1357,8 +1353,8 @@ hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64
   hipError_t e;
   if ((e = launch_zero_bins(L, s, m)) != hipSuccess) return e;
   if ((e = launch_bin(L, g, s, nullptr, nullptr)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, L.stream, s.bin_cnt, s.cell_start,
-                     s.cell_order, m, g.cell_cap);
+  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, L.stream, s.bin_cnt, s.cell_start, m,
+                     g.cell_cap);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, L.stream, s,
                      m, g.cell_cap);
