@@ -268,6 +268,31 @@ md_status md_get_state(md_ctx* ctx, double* x, double* v, double* f);
  * allowed).  Used for force-error reports. */
 md_status md_compute_forces(md_ctx* ctx, double* f, double* rho, double* fp);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the forces,
+ * rho_i and F'_i that md_create + md_set_state + md_build_neighbors +
+ * md_compute_forces give for one box, with no workspace and no device
+ * allocation.  Every intermediate (spline rows, tile tables, sorted state,
+ * bins, neighbour list, status words) lives in a fixed 16 MiB device array
+ * that the library holds on each GPU it runs on until the process ends.
+ * Limits: n_atoms <= MD_STATIC_MAX_ATOMS, at most MD_STATIC_MAX_CELLS
+ * binning cells, tables of at most MD_STATIC_MAX_KNOTS knots,
+ * p->nbr_capacity <= 128, p->cell_capacity <= 64, the full list and one atom
+ * type; past them the call returns MD_E_ARG (MD_E_TABLE for tables) before
+ * touching the device.  Unlike elsewhere, the three tables' coef fields are
+ * DEVICE pointers here ((n_knots-1) x 4 float64 each).  x: device
+ * [n_atoms][3] float64; f: device [n_atoms][3], rho and fp: device
+ * [n_atoms] (any of the three may be NULL); all in the caller's order.
+ * Synchronises the stream.  Calls on one GPU share the array: calls that
+ * overlap in time on one GPU (other threads, other streams) race. */
+#define MD_STATIC_MAX_ATOMS 16384
+#define MD_STATIC_MAX_CELLS 4096
+#define MD_STATIC_MAX_KNOTS 2048
+md_status md_forces_static(const md_params* p, int64_t n_atoms, const double* box,
+                           const md_spline* phi, const md_spline* rho, const md_spline* emb,
+                           const double* x, double* f, double* rho_out, double* fp_out,
+                           void* stream);
+
 /* Counters (synchronises). */
 md_status md_stats(md_ctx* ctx, md_stats_t* out);
 

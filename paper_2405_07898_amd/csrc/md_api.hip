@@ -1418,3 +1418,255 @@ void md_destroy(md_ctx* c) {
 
 }  // extern "C"
 
+// ================================================== allocation-free force evaluation
+//
+// md_forces_static: the force evaluation of md_create + md_set_state +
+// md_build_neighbors + md_compute_forces for one box, with every intermediate
+// (replica and tile tables, spline rows, sorted state, bins, neighbour list,
+// status words) in `scratch`, a fixed device array that each GPU holds until
+// the process ends.  Nothing is allocated: the tables come from the caller's
+// device coefficient arrays through a set-up kernel, and the status returns by
+// one small copy.  Calls that overlap on one GPU share the array and race.
+
+#include <mutex>
+
+static constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+struct StaticDevice {
+  char* ptr = nullptr;  // device address of `scratch` on this GPU
+  int persist_blocks = 0;
+  int lds_max = 0;
+};
+constexpr int kStaticDevices = 64;
+std::mutex g_static_mu;
+StaticDevice g_static[kStaticDevices];
+
+// Address of `scratch` and launch sizes on the current device, looked up once
+// per device (the array's name is a host-side stand-in, not a device address).
+md_status static_device(StaticDevice* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= kStaticDevices) return MD_E_ARG;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticDevice& d = g_static[dev];
+  if (!d.ptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    int cus = 0, lds = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "device attributes");
+    d.persist_blocks = std::max(kXcd, (cus / kXcd) * kXcd);
+    d.lds_max = lds;
+    d.ptr = static_cast<char*>(p);
+  }
+  *out = d;
+  return MD_OK;
+}
+
+// Set-up of one box in the scratch array: replica table, XCD-ordered atom and
+// cell tiles (as md_create lays them out), spline rows from the caller's
+// device coefficients (the host layout of md_create's build_tables, same
+// arithmetic), and zeroed counters.
+__global__ __launch_bounds__(256) void k_static_setup(RepDev rep, Geometry g, State s, Tables t,
+                                                      const double* __restrict__ phi_c,
+                                                      const double* __restrict__ rho_c,
+                                                      const double* __restrict__ emb_c,
+                                                      int64_t ncells) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t0 == 0) *const_cast<RepDev*>(g.reps) = rep;
+  const int64_t ntiles = rep.ntiles;
+  const int64_t aper = (ntiles + kXcd - 1) / kXcd;
+  for (int64_t b = t0; b < g.n_atiles; b += stride) {
+    const int64_t q = (b % kXcd) * aper + b / kXcd;
+    AtomTile a{0, 0, 0, 0};
+    if (q < ntiles) a = AtomTile{0, (int32_t)(64 * q), (int32_t)min<int64_t>(64, g.n - 64 * q), 0};
+    const_cast<AtomTile*>(g.atiles)[b] = a;
+  }
+  const int64_t cper = (ncells + kXcd - 1) / kXcd;
+  for (int64_t b = t0; b < g.n_ctiles; b += stride) {
+    const int64_t q = (b % kXcd) * cper + b / kXcd;
+    const_cast<CellTile*>(g.ctiles)[b] = CellTile{0, q < ncells ? (int32_t)q : -1};
+  }
+  const double a = t.r_inv_dx;
+  for (int64_t k = t0; k < t.nr - 1; k += stride) {
+    const double* r = rho_c + 4 * k;
+    const double* f = phi_c + 4 * k;
+    const_cast<double4*>(t.rho_val)[k] = make_double4(r[0], r[1], r[2], r[3]);
+    const_cast<double4*>(t.phi_val)[k] = make_double4(f[0], f[1], f[2], f[3]);
+    const double r0 = r[1] * a, r1 = 2.0 * r[2] * a, r2 = 3.0 * r[3] * a;
+    const double p0 = f[1] * a, p1 = 2.0 * f[2] * a, p2 = 3.0 * f[3] * a;
+    double2* d3 = const_cast<double2*>(t.dpair3) + 3 * k;
+    d3[0] = make_double2(r0, r1);
+    d3[1] = make_double2(r2, p0);
+    d3[2] = make_double2(p1, p2);
+    const_cast<float4*>(t.rho_val32)[k] =
+        make_float4((float)r[0], (float)r[1], (float)r[2], (float)r[3]);
+    const_cast<float4*>(t.dpair_a32)[k] = make_float4((float)r0, (float)r1, (float)r2, (float)p0);
+    const_cast<float2*>(t.dpair_b32)[k] = make_float2((float)p1, (float)p2);
+  }
+  for (int64_t k = t0; k < t.ne - 1; k += stride) {
+    const double* e = emb_c + 4 * k;
+    const_cast<double4*>(t.emb_val)[k] = make_double4(e[0], e[1], e[2], e[3]);
+  }
+  for (int64_t k = t0; k < SW_WORDS; k += stride) s.status[k] = 0;
+  for (int64_t k = t0; k < 3; k += stride) s.rflag[k] = 0;
+  for (int64_t k = t0; k < ncells; k += stride) {
+    s.bin_cnt[k] = 0;
+    s.cell_stat[3 * k + 0] = s.cell_stat[3 * k + 1] = s.cell_stat[3 * k + 2] = 0;
+  }
+  for (int64_t k = t0; k < g.n; k += stride) {
+    s.cnt[k] = 0;
+    s.frc[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+  }
+}
+
+bool valid_device_spline(const md_spline* s) {
+  return s && s->coef && s->n_knots >= 3 && s->n_knots <= MD_STATIC_MAX_KNOTS &&
+         std::isfinite(s->x0) && std::isfinite(s->inv_dx) && s->inv_dx > 0.0;
+}
+
+}  // namespace
+
+extern "C" md_status md_forces_static(const md_params* p, int64_t n_atoms, const double* box,
+                                      const md_spline* phi, const md_spline* rho,
+                                      const md_spline* emb, const double* x, double* f,
+                                      double* rho_out, double* fp_out, void* stream) {
+  // host-side checks first: nothing touches the device before they pass
+  md_status s = check_params(p);
+  if (s != MD_OK) return s;
+  if (p->list_mode != MD_LIST_FULL || p->n_types > 1 || p->nbr_capacity > 128 ||
+      p->cell_capacity > 64 || !x || !box)
+    return MD_E_ARG;
+  if (n_atoms < 1 || n_atoms > MD_STATIC_MAX_ATOMS) return MD_E_ARG;
+  if (!valid_device_spline(phi) || !valid_device_spline(rho) || !valid_device_spline(emb))
+    return MD_E_TABLE;
+  if (phi->n_knots != rho->n_knots || phi->inv_dx != rho->inv_dx || phi->x0 != 0.0 ||
+      rho->x0 != 0.0)
+    return MD_E_TABLE;
+  if ((double)(rho->n_knots - 1) / rho->inv_dx < p->r_cut * (1.0 - 1e-12)) return MD_E_TABLE;
+  std::vector<RepHost> reps;
+  if ((s = gather_reps(p, 1, &n_atoms, box, &reps)) != MD_OK) return s;
+  const LayoutSizes ls = layout(p, 1, reps);
+  if (ls.cells > MD_STATIC_MAX_CELLS) return MD_E_ARG;
+  if (carve(nullptr, p, 1, ls, rho->n_knots, emb->n_knots, nullptr) > kScratchBytes)
+    return MD_E_ARG;
+
+  StaticDevice dev;
+  if ((s = static_device(&dev)) != MD_OK) return s;
+  Buffers b;
+  carve(dev.ptr, p, 1, ls, rho->n_knots, emb->n_knots, &b);
+
+  RepDev rd;
+  memset(&rd, 0, sizeof(rd));
+  for (int k = 0; k < 3; ++k) {
+    rd.box[k] = reps[0].box[k];
+    rd.nc[k] = reps[0].nc[k];
+    rd.inv_cell[k] = (double)reps[0].nc[k] / reps[0].box[k];
+  }
+  rd.n_atoms = (int32_t)n_atoms;
+  rd.ncell = rd.nc[0] * rd.nc[1] * rd.nc[2];
+  rd.open = reps[0].open;
+  rd.ntiles = (int32_t)((n_atoms + 63) / 64);
+
+  Geometry g{};
+  g.reps = b.reps;
+  g.atiles = b.atiles;
+  g.ctiles = b.ctiles;
+  g.n = ls.n;
+  g.n_atiles = (int32_t)ls.atile_blocks;
+  g.n_ctiles = (int32_t)ls.ctile_blocks;
+  g.n_rep = 1;
+  g.nbr_cap = p->nbr_capacity;
+  g.cell_cap = p->cell_capacity;
+  g.rc2 = p->r_cut * p->r_cut;
+  g.rl2 = (p->r_cut + p->skin) * (p->r_cut + p->skin);
+  g.lim2 = 0.25 * p->skin * p->skin;
+  g.dt = p->dt;
+  g.acc = p->ftm2v / p->mass;
+  for (int q = 0; q < kMaxTypes; ++q) g.acc_t[q] = g.acc;
+  g.rc2f = (float)g.rc2;
+
+  Tables t{};
+  t.rho_val = b.rho_val;
+  t.phi_val = b.phi_val;
+  t.dpair3 = b.dpair3;
+  t.emb_val = b.emb_val;
+  t.rho_val32 = b.rho_val32;
+  t.dpair_a32 = b.dpair_a32;
+  t.dpair_b32 = b.dpair_b32;
+  t.r_inv_dx = rho->inv_dx;
+  t.r_inv_dx32 = (float)rho->inv_dx;
+  t.e_x0 = emb->x0;
+  t.e_inv_dx = emb->inv_dx;
+  t.nr = rho->n_knots;
+  t.ne = emb->n_knots;
+  if (force_lds_bytes(t, p->precision) > (size_t)dev.lds_max ||
+      density_lds_bytes(t, p->precision) > (size_t)dev.lds_max)
+    return MD_E_TABLE;
+
+  State st{};
+  st.pos = b.pos0;
+  st.pos_alt = b.pos1;
+  st.vel = b.vel;
+  st.xref = b.xref;
+  st.frc = b.frc;
+  st.rho = b.rho;
+  st.epair = b.epair;
+  st.id = b.id;
+  st.cell_of = b.cell_of;
+  st.nbr = b.nbr;
+  st.cnt = b.cnt;
+  st.bin_cnt = b.bin_cnt;
+  st.bin_idx = b.bin_idx;
+  st.cell_start = b.cell_start;
+  st.cell_stat = b.cell_stat;
+  st.status = b.status;
+  st.rflag = b.rflag;
+  st.sort_pos = b.sort_pos;
+  st.sort_vel = b.sort_vel;
+  st.sort_id = b.sort_id;
+  st.partial = b.partial;
+
+  Launch L{};
+  L.stream = reinterpret_cast<hipStream_t>(stream);
+  L.atile_blocks = (int32_t)ls.atile_blocks;
+  L.ctile_blocks = (int32_t)ls.ctile_blocks;
+  L.persist_blocks = dev.persist_blocks;
+  const int lpa = p->lanes_per_atom ? p->lanes_per_atom : auto_lpa(ls.n);
+
+  // the kernels' dynamic LDS limits follow this call's table sizes
+  hipError_t e = allow_pair_lds(t, p->precision);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipFuncSetAttribute");
+  const int64_t setup_items = std::max<int64_t>({ls.n, ls.cells, (int64_t)ls.atile_blocks,
+                                                 (int64_t)ls.ctile_blocks, (int64_t)t.nr,
+                                                 (int64_t)t.ne, (int64_t)SW_WORDS});
+  hipLaunchKernelGGL(k_static_setup, dim3((unsigned)std::min<int64_t>((setup_items + 255) / 256, 1024)),
+                     dim3(256), 0, L.stream, rd, g, st, t, phi->coef, rho->coef, emb->coef,
+                     (int64_t)ls.cells);
+  e = hipGetLastError();
+  // the sequence of md_set_state, md_build_neighbors and md_compute_forces
+  if (e == hipSuccess) e = launch_import(L, g, st, x, nullptr);
+  if (e == hipSuccess) e = launch_sort(L, g, st, ls.cells);
+  if (e == hipSuccess) e = launch_zero_bins(L, st, ls.cells);
+  if (e == hipSuccess) e = launch_bin(L, g, st, nullptr, nullptr);
+  if (e == hipSuccess) e = launch_build(L, g, st, nullptr, nullptr);
+  if (e == hipSuccess) e = launch_zero_bins(L, st, ls.cells);
+  if (e == hipSuccess)
+    e = launch_density(L, g, st, t, p->precision, lpa, st.pos, nullptr, nullptr, nullptr,
+                       ls.cells, true);
+  if (e == hipSuccess) e = launch_force_only(L, g, st, t, p->precision, lpa, st.pos);
+  if (e == hipSuccess) e = launch_export(L, g, st, nullptr, nullptr, f, rho_out, fp_out, 0.0);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "md_forces_static launch");
+  int32_t bits = 0;
+  e = hipMemcpyAsync(&bits, st.status + SW_BITS, sizeof(int32_t), hipMemcpyDeviceToHost, L.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L.stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "md_forces_static status");
+  return status_code(bits);
+}

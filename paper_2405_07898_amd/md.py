@@ -20,6 +20,7 @@ MD_E_ARG, MD_E_BOX, MD_E_TABLE, MD_E_NBR_OVERFLOW, MD_E_CELL_OVERFLOW = -1, -2, 
 MD_E_NONFINITE, MD_E_HIP, MD_E_ORDER, MD_E_LOST_ATOM, MD_E_WORKSPACE = -6, -7, -8, -9, -10
 MD_E_STALL = -11
 MD_W_RHO_RANGE = 1
+MD_STATIC_MAX_ATOMS, MD_STATIC_MAX_CELLS, MD_STATIC_MAX_KNOTS = 16384, 4096, 2048
 MD_FP64, MD_MIXED = 0, 1
 MD_LIST_FULL, MD_LIST_HALF = 0, 1
 MD_LAUNCH_GRAPH, MD_LAUNCH_PERSISTENT = 0, 1
@@ -62,6 +63,7 @@ EXPORTED = [
     "md_get_replica_schedule", "md_autotune", "md_last_error",
     "md_status_string", "md_destroy", "md_create_multi", "md_set_types",
     "md_fm_workspace_size", "md_fm_create", "md_fm_forward", "md_fm_backward", "md_fm_destroy",
+    "md_forces_static",
 ]
 
 
@@ -109,6 +111,8 @@ def lib():
             "md_fm_forward": (i32, [vp, vp, vp, vp, P(d), vp]),
             "md_fm_backward": (i32, [vp, d, vp, vp, vp]),
             "md_fm_destroy": (None, [vp]),
+            "md_forces_static": (i32, [P(md_params), i64, P(d), P(md_spline), P(md_spline),
+                                       P(md_spline), vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name, None)
