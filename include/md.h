@@ -254,6 +254,13 @@ md_status md_build_neighbors(md_ctx* ctx);
  * status; n < 0 is MD_E_ARG. */
 md_status md_step(md_ctx* ctx, int64_t n);
 
+/* Capture, without running them, the graphs that md_step(n) would launch
+ * from the current state (the chunk graph and the shorter graphs of the
+ * left-over steps), so that the next md_step(n) spends no time capturing.
+ * Changes no state; graphs are dropped again by md_set_schedule.  Nothing to
+ * do with MD_LAUNCH_PERSISTENT.  Requires md_build_neighbors. */
+md_status md_prepare(md_ctx* ctx, int64_t n);
+
 /* Potential and kinetic energy per replica (host arrays of n_rep doubles;
  * either may be NULL), with on-step velocities.  Fixed-order reductions:
  * bitwise reproducible. */

@@ -469,6 +469,9 @@ md_status capture_steps(md_ctx* c, int len, hipGraphExec_t* out) {
     *out = nullptr;
     return hip_fail(c, e, "hipGraphInstantiate");
   }
+  // move the graph to the device now, so that its first launch costs no more than later ones
+  e = hipGraphUpload(*out, c->L.stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphUpload");
   return MD_OK;
 }
 
@@ -1040,6 +1043,8 @@ md_status md_build_neighbors(md_ctx* c) {
   }
   c->chunks_since_sort = 0;
   HIPC(c, hipMemsetAsync(c->status + SW_STEPS, 0, 2 * sizeof(int32_t), c->L.stream));
+  // a clean rollback point exists from here on
+  HIPC(c, launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, false));
   int32_t w[SW_WORDS];
   if ((s = read_status(c, w)) != MD_OK) return s;
   s = status_code(w[SW_BITS]);
@@ -1053,7 +1058,10 @@ md_status md_step(md_ctx* c, int64_t n) {
   md_status s;
   int64_t done = 0;
   const int chunk = c->p.chunk_steps;
-  HIPC(c, launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, false));
+  // every graph and persistent launch below snapshots first; the persistent
+  // form's kernel-by-kernel steps need one from here
+  if (c->p.launch_mode == MD_LAUNCH_PERSISTENT)
+    HIPC(c, launch_snapshot(c->L, c->g, c->st[c->cur], c->snap_pos, c->snap_vel, false));
   while (done < n) {
     if (c->cur == 0 && n - done >= chunk) {
       if (c->p.sort_every > 0 && c->chunks_since_sort >= c->p.sort_every) {
@@ -1101,6 +1109,30 @@ md_status md_step(md_ctx* c, int64_t n) {
     HIPC(c, hipStreamSynchronize(c->L.stream));
     return s;
   }
+  return s;
+}
+
+md_status md_prepare(md_ctx* c, int64_t n) {
+  if (!c || n < 0) return MD_E_ARG;
+  if (!c->built) return MD_E_ORDER;
+  if (c->p.launch_mode == MD_LAUNCH_PERSISTENT) return MD_OK;
+  // walk md_step's launch plan from the current buffer parity
+  const int chunk = c->p.chunk_steps;
+  const int saved = c->cur;
+  md_status s = MD_OK;
+  for (int64_t done = 0; done < n && s == MD_OK;) {
+    if (c->cur == 0 && n - done >= chunk) {
+      s = capture_chunk(c);
+      done += (n - done) / chunk * chunk;
+    } else {
+      const int len = (int)std::min<int64_t>(n - done, chunk - 1);
+      hipGraphExec_t ge = nullptr;
+      s = tail_graph(c, len, &ge);
+      if (len & 1) c->cur = 1 - c->cur;
+      done += len;
+    }
+  }
+  c->cur = saved;
   return s;
 }
 

@@ -57,7 +57,8 @@ class md_stats_t(C.Structure):
 _lib = None
 
 EXPORTED = [
-    "md_workspace_size", "md_workspace_bytes", "md_init", "md_init_batch", "md_create", "md_set_state", "md_build_neighbors", "md_step",
+    "md_workspace_size", "md_workspace_bytes", "md_init", "md_init_batch", "md_create",
+    "md_set_state", "md_build_neighbors", "md_step", "md_prepare",
     "md_energy", "md_get_state", "md_compute_forces", "md_stats", "md_get_cells",
     "md_get_neighbors", "md_launch_pass", "md_set_schedule", "md_set_replica_schedule",
     "md_get_replica_schedule", "md_autotune", "md_last_error",
@@ -91,6 +92,7 @@ def lib():
             "md_set_state": (i32, [vp, vp, vp]),
             "md_build_neighbors": (i32, [vp]),
             "md_step": (i32, [vp, i64]),
+            "md_prepare": (i32, [vp, i64]),
             "md_energy": (i32, [vp, P(d), P(d)]),
             "md_get_state": (i32, [vp, vp, vp, vp]),
             "md_compute_forces": (i32, [vp, vp, vp, vp]),
@@ -263,6 +265,10 @@ class System:
     def step(self, n: int, check: bool = True):
         rc = lib().md_step(self.ctx, int(n))
         return _check(rc, "md_step", self.ctx) if check else rc
+
+    def prepare(self, n: int):
+        """Capture the graphs step(n) will launch, so that step(n) only launches them."""
+        return _check(lib().md_prepare(self.ctx, int(n)), "md_prepare", self.ctx)
 
     def energy(self):
         pe = np.zeros(self.n_rep)

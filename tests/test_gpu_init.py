@@ -190,3 +190,32 @@ def test_cell_overflow_at_a_resort_rolls_back_cleanly(md, tabs, oracle_lib):
                             r_cut=RC, skin=skin, ftm2v=configs.FTM2V, cap=256)
     assert out["code"] == 0
     _close(x.cpu().numpy(), v.cpu().numpy(), box, out)
+
+
+def test_prepare_captures_without_stepping(md, tabs):
+    """md_prepare(n) captures the graphs of md_step(n) from the odd position
+    buffer (a shorter graph, chunks, another shorter graph) and changes no
+    state: the step count stays, and the run after it is bitwise the run
+    without it."""
+    box = configs.small_box(6, seed=86, temperature=2000.0, sigma_x=0.05)
+    _say(f"[gpu] md_prepare n={box.n}")
+
+    def run(prepare):
+        s = md.System(_params(md, chunk_steps=20, sort_every=0), tabs, [box.n],
+                      box.box[None, :])
+        s.set_state(box.x, box.v)
+        s.build_neighbors()
+        s.step(3)
+        if prepare:
+            s.prepare(45)
+            assert s.stats()["steps"] == 3
+        s.step(45)
+        x, v, f = (t.cpu().numpy() for t in s.get_state())
+        st = s.stats()
+        s.close()
+        return x, v, f, st
+
+    xa, va, fa, sa = run(True)
+    xb, vb, fb, sb = run(False)
+    assert sa["steps"] == sb["steps"] == 48
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(fa, fb)
