@@ -92,11 +92,11 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def load_traffic(n_atoms: int, n_l: float):
+def load_traffic(n_atoms: int, n_l: float, lpa: int):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter runs, if they were taken on the current kernel sources, at the same
-    atom count and at a mean list length within 2 % of this state's; else None
-    with the reason."""
+    atom count and lanes per atom and at a mean list length within 2 % of this
+    state's; else None with the reason."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter file"
     with open(TRAFFIC_FILE) as f:
@@ -104,7 +104,8 @@ def load_traffic(n_atoms: int, n_l: float):
     if t.get("kernel_source_sha256") != source_hash():
         return None, "kernel sources changed since the counters were taken"
     for e in t.get("entries", []):
-        if e.get("n_atoms") == n_atoms and abs(e.get("mean_list_length", -1.0) - n_l) <= 0.02 * n_l:
+        if (e.get("n_atoms") == n_atoms and e.get("lanes_per_atom") == lpa
+                and abs(e.get("mean_list_length", -1.0) - n_l) <= 0.02 * n_l):
             return e.get("bytes_per_launch"), t.get("summary")
     return None, "no counter run at this atom count and list length"
 
@@ -242,7 +243,7 @@ def bench_headline(torch, md, configs, tabs, args, copy_gbs):
     # the roofline that binds: intensity below the float64 ridge -> HBM
     ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     bound = "hbm" if flops / byts < ridge else "alu"
-    traffic, traffic_note = load_traffic(box.n, n_l)
+    traffic, traffic_note = load_traffic(box.n, n_l, lpa)
     roof = {"bound": bound, "kernel": "k_force_integrate<fp64>",
             "achieved": round(gbs, 1) if bound == "hbm" else round(tfl, 3),
             "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_PEAK_TFLOPS,
