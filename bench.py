@@ -61,21 +61,25 @@ def log(msg: str) -> None:
 def force_pass_bytes(n_atoms: int, n_l: float, mixed: bool) -> float:
     """Algorithmic HBM bytes of one force+integrate launch.
 
-    Per atom: x (24) + F' (8, 4 mixed) + list length (4) + list entries (4 n_l)
-    + v read and write (48) + new x (24) + x_ref (24) = 156 + 4 n_l less the
-    force written and read back and x re-read by the separate integration
-    (fused away): 132 + 4 n_l (mixed 128 + 4 n_l).  Neighbour gathers are
-    cache-served and not counted.
+    Per atom: x (24) + F' (8) + list length (4) + list entries (4 n_l) + v read
+    and write (48) + new x (24) + x_ref (24) = 132 + 4 n_l; the unfused pair
+    (force 60 + 4 n_l, integration 144) less the force written and read back
+    and x read again.  The mixed form reads the atom's 16-byte record
+    (fixed-point position and F') in place of F' and writes the record of the
+    new position: 156 + 4 n_l.  Neighbour gathers are cache-served and not
+    counted.
     """
-    per = 24 + (4 if mixed else 8) + 4 + 4 * n_l + 48 + 24 + 24
+    per = (24 + 8 + 4 + 4 * n_l + 48 + 24 + 24) if not mixed else \
+        (24 + 16 + 4 + 4 * n_l + 48 + 24 + 16 + 24)
     return n_atoms * per
 
 
-def density_pass_bytes(n_atoms: int, n_l: float) -> float:
+def density_pass_bytes(n_atoms: int, n_l: float, mixed: bool = False) -> float:
     """Algorithmic bytes of one density launch: x (24) + list length (4) + list
-    entries (4 n_l) + F' written (8) = 36 + 4 n_l per atom."""
-    return n_atoms * (36 + 4 * n_l)
-
+    entries (4 n_l) + F' written (8) = 36 + 4 n_l per atom.  The mixed form
+    reads the atom's 16-byte record in place of x and also writes F' into it
+    (4): 32 + 4 n_l."""
+    return n_atoms * ((16 + 4 + 8 + 4 if mixed else 24 + 4 + 8) + 4 * n_l)
 
 def force_pass_flops(n_atoms: int, n_l: float, n_int: float) -> float:
     """Algorithmic flops (paper Table "flopmodel"): 9 per list entry (distance and
@@ -373,11 +377,16 @@ def bench_c3(torch, md, configs, tabs, args):
     s64_eval = None
     for name, prec in (("fp64", md.MD_FP64), ("mixed", md.MD_MIXED)):
         log(f"c3 {name}: n={big.n}")
-        sb = make_system(md, big, tabs, precision=prec, lpa=args.lpa)
         lpa = args.lpa
         if args.lpa == 0:
-            lpa, us = sb.autotune(20)
-            log(f"  autotune: {lpa} lanes per atom ({us:.1f} us per density+force)")
+            # tuned on a copy of the box after 200 steps: the timed run spends
+            # almost all its steps in the hot, disordered state, not the lattice
+            sw = make_system(md, big, tabs, precision=prec, lpa=2)
+            sw.step(200)
+            lpa, us = sw.autotune(20)
+            sw.close()
+            log(f"  autotune (after 200 steps): {lpa} lanes per atom ({us:.1f} us per density+force)")
+        sb = make_system(md, big, tabs, precision=prec, lpa=lpa)
         st0 = sb.stats()
         total = 0.0
         done = 0
@@ -401,7 +410,7 @@ def bench_c3(torch, md, configs, tabs, args):
                      "force_pass_us": round(fu, 3),
                      "force_pass_hbm_frac": round(b2 / (fu * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                      "density_pass_us": round(du, 3),
-                     "density_pass_hbm_frac": round(density_pass_bytes(big.n, nlb) / (du * 1e-6)
+                     "density_pass_hbm_frac": round(density_pass_bytes(big.n, nlb, prec == md.MD_MIXED) / (du * 1e-6)
                                                     / 1e9 / HBM_PEAK_GBS, 4),
                      "mean_list_length": round(nlb, 3),
                      "rebuilds": int(stb["rebuilds"] - st0["rebuilds"])}

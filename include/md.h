@@ -64,7 +64,11 @@ typedef int32_t md_status;
 #define MD_FP64 0  /* everything in float64 */
 #define MD_MIXED 1 /* pair terms, rho_i and force sums in float32 with compensated
                       (TwoSum) accumulation; positions, velocities, integration
-                      and energy totals in float64 */
+                      and energy totals in float64.  The pair passes take the
+                      separations from a 16-byte record per atom: the position
+                      in 32-bit fixed point (2^32 quanta per periodic box
+                      length, so integer wrap-around is the minimum image;
+                      2^26 per A in an open dimension) and F' in float32 */
 
 /* Neighbour-list form of the pair passes.
  * MD_LIST_FULL: every atom walks both directions of each pair and writes only

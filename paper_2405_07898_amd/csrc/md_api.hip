@@ -189,6 +189,7 @@ struct Buffers {
   float4 *rho_val32, *dpair_a32;
   float2* dpair_b32;
   double4 *pos0, *pos1, *vel, *xref, *frc;
+  uint4 *rec0, *rec1, *sort_rec, *snap_rec;
   double *rho, *epair;
   int32_t *id, *cell_of, *cnt;
   uint32_t* nbr;
@@ -222,6 +223,15 @@ int multi_pair_row(int nt, int a, int b) {
   return nt + a * nt - a * (a - 1) / 2 + (b - a);
 }
 
+// Fixed-point scales of the mixed form's positions (see RepDev).
+void set_quanta(RepDev& d) {
+  for (int k = 0; k < 3; ++k) {
+    const bool open = (d.open >> k) & 1;
+    d.qinv[k] = open ? 67108864.0 : 4294967296.0 / d.box[k];
+    d.qs[k] = open ? (float)(1.0 / 67108864.0) : (float)(d.box[k] / 4294967296.0);
+  }
+}
+
 size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s, int nr, int ne,
              Buffers* b) {
   Carve c;
@@ -244,6 +254,13 @@ size_t carve(char* base, const md_params* p, int32_t n_rep, const LayoutSizes& s
   o.vel = c.take<double4>(N);
   o.xref = c.take<double4>(N);
   o.frc = c.take<double4>(N);
+  o.rec0 = o.rec1 = o.sort_rec = o.snap_rec = nullptr;
+  if (p->precision == MD_MIXED) {
+    o.rec0 = c.take<uint4>(N);
+    o.rec1 = c.take<uint4>(N);
+    o.sort_rec = c.take<uint4>(N);
+    o.snap_rec = c.take<uint4>(N);
+  }
   o.rho = c.take<double>(N);
   o.epair = c.take<double>(N);
   o.id = c.take<int32_t>(N);
@@ -703,6 +720,7 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
     d.cell0 = (int32_t)c0;
     d.ncell = d.nc[0] * d.nc[1] * d.nc[2];
     d.open = reps[r].open;
+    set_quanta(d);
     d.tile0 = (int32_t)at.size();
     d.ntiles = (int32_t)((reps[r].n + 63) / 64);
     for (int64_t t0 = 0; t0 < reps[r].n; t0 += 64)
@@ -841,6 +859,8 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   State base{};
   base.vel = b.vel;
   base.xref = b.xref;
+  base.sort_rec = b.sort_rec;
+  base.snap_rec = b.snap_rec;
   base.frc = b.frc;
   base.rho = b.rho;
   base.epair = b.epair;
@@ -904,6 +924,10 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
   c->st[0].pos_alt = b.pos1;
   c->st[1].pos = b.pos1;
   c->st[1].pos_alt = b.pos0;
+  c->st[0].rec = b.rec0;
+  c->st[0].rec_alt = b.rec1;
+  c->st[1].rec = b.rec1;
+  c->st[1].rec_alt = b.rec0;
   c->pos_buf[0] = b.pos0;
   c->pos_buf[1] = b.pos1;
   c->snap_pos = b.snap_pos;
@@ -1605,6 +1629,7 @@ extern "C" md_status md_forces_static(const md_params* p, int64_t n_atoms, const
   rd.n_atoms = (int32_t)n_atoms;
   rd.ncell = rd.nc[0] * rd.nc[1] * rd.nc[2];
   rd.open = reps[0].open;
+  set_quanta(rd);
   rd.ntiles = (int32_t)((n_atoms + 63) / 64);
 
   Geometry g{};
@@ -1648,6 +1673,10 @@ extern "C" md_status md_forces_static(const md_params* p, int64_t n_atoms, const
   st.pos_alt = b.pos1;
   st.vel = b.vel;
   st.xref = b.xref;
+  st.rec = b.rec0;
+  st.rec_alt = b.rec1;
+  st.sort_rec = b.sort_rec;
+  st.snap_rec = b.snap_rec;
   st.frc = b.frc;
   st.rho = b.rho;
   st.epair = b.epair;

@@ -158,17 +158,19 @@ __device__ __forceinline__ double lane_sum_sym(double v) {
 
 // List entries in flight per lane in the pair passes.
 constexpr int kBatch = 4;
+// The same in the mixed form's force pass (16-byte neighbour records).
+constexpr int kBatchMixed = 4;
 
 // The next kBatch list entries of atom i for this lane (entries past the list
 // end read as the atom itself with no image shift).
-template <int LPA>
+template <int LPA, int B>
 __device__ __forceinline__ void load_entries(const uint32_t* __restrict__ nbr, uint32_t N,
                                              uint32_t i, int k0, int m, uint32_t self_e,
-                                             uint32_t (&e)[kBatch]) {
+                                             uint32_t (&e)[B]) {
   uint32_t off = ((uint32_t)k0 * N + i) * 4u;
   const uint32_t step = (uint32_t)LPA * N * 4u;
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
+  for (int u = 0; u < B; ++u) {
     e[u] = (k0 + u * LPA < m) ? ld32(nbr, off) : self_e;
     off += step;
   }

@@ -64,6 +64,13 @@ struct RepDev {
   int32_t ntiles;  // atom tiles of the replica
   int32_t open;    // bit d set: dimension d is open (not periodic)
   int32_t pad;
+  // fixed-point positions of the mixed form: q = round(x * qinv) modulo 2^32,
+  // x = q * qs.  A periodic dimension maps L to 2^32, so integer wrap-around is
+  // the periodic wrap and q_j - q_i (int32) is the minimum image; an open one
+  // uses 2^26 quanta per A (differences up to 32 A).
+  double qinv[3];
+  float qs[3];
+  int32_t pad2;
 };
 
 struct AtomTile {
@@ -131,6 +138,13 @@ struct State {
   double4* pos_alt;  // other position buffer (leap-frog ping-pong)
   double4* vel;      // velocity (half step inside md_step)
   double4* xref;     // positions at the last list build
+  // mixed form only (null otherwise): per slot {x, y, z in fixed point, F'(rho_i)
+  // float bits}, the 16-byte record both pair passes gather; kept beside pos
+  // (same buffer parity) by every kernel that writes positions
+  uint4* rec;
+  uint4* rec_alt;
+  uint4* sort_rec;
+  uint4* snap_rec;
   double4* frc;      // forces when requested
   double* rho;       // rho_i when requested
   double* epair;     // 1/2 sum phi when requested

@@ -44,6 +44,18 @@ __device__ __forceinline__ double4 wrap_pos(double4 p, const RepDev& rp, bool& b
   return make_double4(q[0], q[1], q[2], p.w);
 }
 
+// Fixed-point coordinate of the mixed form (RepDev::qinv): round to nearest,
+// then the low 32 bits (the periodic wrap in a periodic dimension).
+__device__ __forceinline__ uint32_t quantize(double x, double qinv) {
+  return (uint32_t)(unsigned long long)__double2ll_rn(x * qinv);
+}
+
+// The mixed form's record of a position (F' slot cleared).
+__device__ __forceinline__ uint4 pos_record(const RepDev& rp, double x, double y, double z) {
+  return make_uint4(quantize(x, rp.qinv[0]), quantize(y, rp.qinv[1]), quantize(z, rp.qinv[2]),
+                    0u);
+}
+
 // ============================================================ import / export
 
 __global__ __launch_bounds__(64) void k_import(Geometry g, State s, const double* __restrict__ x,
@@ -57,6 +69,7 @@ __global__ __launch_bounds__(64) void k_import(Geometry g, State s, const double
       wrap_pos(make_double4(x[3 * i + 0], x[3 * i + 1], x[3 * i + 2], 0.0), rp, bad);
   if (bad) set_bits(s.status, ST_LOST);
   s.pos[i] = p;
+  if (s.rec) s.rec[i] = pos_record(rp, p.x, p.y, p.z);
   s.vel[i] = v ? make_double4(v[3 * i + 0], v[3 * i + 1], v[3 * i + 2], 0.0)
                : make_double4(0.0, 0.0, 0.0, 0.0);
   s.id[i] = (int32_t)i;
@@ -148,6 +161,7 @@ __device__ __forceinline__ void bin_tile(const Geometry& g, const State& s, cons
   }
   s.pos[i] = p;
   s.xref[i] = p;
+  if (s.rec) s.rec[i] = pos_record(rp, p.x, p.y, p.z);
   int32_t c[3];
   const double q[3] = {p.x, p.y, p.z};
 #pragma unroll
@@ -529,6 +543,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(State s, int64_t m, int32_
     s.sort_vel[base + r] = s.vel[e];
     s.sort_id[base + r] = key;
     if (s.type) s.sort_type[base + r] = s.type[e];
+    if (s.rec) s.sort_rec[base + r] = s.rec[e];
   }
 }
 
@@ -541,6 +556,7 @@ __global__ __launch_bounds__(256) void k_sort_copyback(State s, int64_t n, int64
     s.vel[k] = s.sort_vel[k];
     s.id[k] = s.sort_id[k];
     if (s.type) s.type[k] = s.sort_type[k];
+    if (s.rec) s.rec[k] = s.sort_rec[k];
   }
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
@@ -581,8 +597,15 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
   const uint32_t N = (uint32_t)g.n;
   const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
   const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-  const double2 pxy = *reinterpret_cast<const double2*>(&pos[i]);
-  const double pz = pos[i].z;
+  double2 pxy = make_double2(0.0, 0.0);
+  double pz = 0.0;
+  uint4 qi = make_uint4(0u, 0u, 0u, 0u);
+  if (PREC == 0) {
+    pxy = *reinterpret_cast<const double2*>(&pos[i]);
+    pz = pos[i].z;
+  } else {
+    qi = s.rec[i];
+  }
   const int last = t.nr - 2;
   double acc = 0.0;
   float sum = 0.0f, comp = 0.0f;
@@ -596,20 +619,25 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
   for (int k0 = sub; k0 < m; k0 += kstep) {
     double2 qxy[kBatch];
     double qz[kBatch];
+    uint4 qr[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const uint32_t off = (e[u] & kIndexMask) * 32u;
-      qxy[u] = ld32(pos2, off);
-      qz[u] = ld32(posd, off + 16u);
+      if (PREC == 0) {
+        const uint32_t off = (e[u] & kIndexMask) * 32u;
+        qxy[u] = ld32(pos2, off);
+        qz[u] = ld32(posd, off + 16u);
+      } else {
+        qr[u] = ld32(s.rec, (e[u] & kIndexMask) * 16u);
+      }
     }
     uint32_t en[kBatch];
     load_entries<LPA>(s.nbr, N, (uint32_t)i, k0 + kstep, m, self_e, en);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const bool v = k0 + u * LPA < m;
-      double dx, dy, dz;
-      separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
       if (PREC == 0) {
+        double dx, dy, dz;
+        separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
         const double4* tab = reinterpret_cast<const double4*>(lds_tab);
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const bool in = v && r2 < g.rc2;
@@ -621,7 +649,11 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
         if (in) acc += fma(fma(fma(c.w, tt, c.z), tt, c.y), tt, c.x);
       } else {
         const float4* tab = reinterpret_cast<const float4*>(lds_tab);
-        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        // separation from the fixed-point records (int32 wrap-around gives the
+        // minimum image, the listed one for every list pair)
+        const float fx = (float)(int32_t)(qr[u].x - qi.x) * rp.qs[0];
+        const float fy = (float)(int32_t)(qr[u].y - qi.y) * rp.qs[1];
+        const float fz = (float)(int32_t)(qr[u].z - qi.z) * rp.qs[2];
         const float r2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
         const bool in = v && r2 < g.rc2f;
         const float rr = in ? r2 : 1.0f;
@@ -640,7 +672,9 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
   return (double)sum + (double)comp;
 }
 
-// F'(rho_i) from the embedding table (float64 for both forms) into pos[i].w.
+// F'(rho_i) from the embedding table (float64 for both forms) into pos[i].w;
+// the mixed form also into its record's fourth word (float32), which the
+// force pass gathers with the fixed-point position.
 template <int PREC>
 __device__ __forceinline__ void store_fprime(const State& s, const Tables& t, double4* pos,
                                              int64_t i, double rho_i, int want_rho) {
@@ -651,7 +685,10 @@ __device__ __forceinline__ void store_fprime(const State& s, const Tables& t, do
   const double te = fmin(xe - (double)ke, 1.0);
   const double4 ce = t.emb_val[ke];
   double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
-  if (PREC != 0) fp = (double)(float)fp;
+  if (PREC != 0) {
+    fp = (double)(float)fp;
+    s.rec[i].w = __float_as_uint((float)fp);
+  }
   pos[i].w = fp;
   if (want_rho) s.rho[i] = rho_i;
   if (xe > (double)(t.ne - 1)) set_bits(s.status, ST_RHO_RANGE);
@@ -715,22 +752,29 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
   const int last = t.nr - 2;
   double ax = 0.0, ay = 0.0, az = 0.0;
   float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
-  const float fpi = (float)pi.w;
-  const int kstep = LPA * kBatch;
-  uint32_t e[kBatch];
+  // mixed form: the atom's own record (fixed-point position, F' in float32)
+  const uint4 qi = PREC == 0 ? make_uint4(0u, 0u, 0u, 0u) : s.rec[i];
+  const float fpi = PREC == 0 ? 0.0f : __uint_as_float(qi.w);
+  constexpr int kB = PREC == 0 ? kBatch : kBatchMixed;
+  const int kstep = LPA * kB;
+  uint32_t e[kB];
   load_entries<LPA>(s.nbr, N, (uint32_t)i, sub, m, self_e, e);
   for (int k0 = sub; k0 < m; k0 += kstep) {
-    double4 q[kBatch];
+    double4 q[kB];
+    uint4 qr[kB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) q[u] = ld32(pos, (e[u] & kIndexMask) * 32u);
-    uint32_t en[kBatch];
+    for (int u = 0; u < kB; ++u) {
+      if (PREC == 0) q[u] = ld32(pos, (e[u] & kIndexMask) * 32u);
+      else qr[u] = ld32(s.rec, (e[u] & kIndexMask) * 16u);
+    }
+    uint32_t en[kB];
     load_entries<LPA>(s.nbr, N, (uint32_t)i, k0 + kstep, m, self_e, en);
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < kB; ++u) {
       const bool v = k0 + u * LPA < m;
-      double dx, dy, dz;
-      separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
       if (PREC == 0) {
+        double dx, dy, dz;
+        separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
         const double2* tab = reinterpret_cast<const double2*>(lds_tab);
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const bool in = v && r2 < g.rc2;
@@ -752,7 +796,11 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
       } else {
         const float4* ta = reinterpret_cast<const float4*>(lds_tab);
         const float2* tb = reinterpret_cast<const float2*>(ta + (t.nr - 1));
-        const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
+        // separation from the fixed-point difference: int32 wrap-around gives
+        // the minimum image, which is the listed image for every list pair
+        const float ex = (float)(int32_t)(qr[u].x - qi.x) * rp.qs[0];
+        const float ey = (float)(int32_t)(qr[u].y - qi.y) * rp.qs[1];
+        const float ez = (float)(int32_t)(qr[u].z - qi.z) * rp.qs[2];
         const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
         const bool in = v && r2 < g.rc2f;
         const float rr = in ? r2 : 1.0f;
@@ -764,7 +812,7 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
         const float2 B = tb[kk];
         const float drho = fmaf(fmaf(A.z, tt, A.y), tt, A.x);
         const float dphi = fmaf(fmaf(B.y, tt, B.x), tt, A.w);
-        const float sc = fmaf(fpi + (float)q[u].w, drho, dphi) * rinv;
+        const float sc = fmaf(fpi + __uint_as_float(qr[u].w), drho, dphi) * rinv;
         if (in) {
           two_sum_acc(sx, cx, sc * ex);
           two_sum_acc(sy, cy, sc * ey);
@@ -773,7 +821,7 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
       }
     }
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) e[u] = en[u];
+    for (int u = 0; u < kB; ++u) e[u] = en[u];
   }
   if (PREC == 0) {
     fx = lane_sum_sym<LPA>(ax);
@@ -805,9 +853,9 @@ __device__ __forceinline__ void fill_force_table(void* lds, const Tables& t) {
 // Leap-frog update of atom i from its force (Eq. leapfrog): v <- v + dt F
 // ftm2v/m, x' <- x + dt v into pos_out; returns whether it moved more than
 // skin/2 since the last list build (also true for NaN).
-__device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, int64_t i, double4 pi,
-                                         double4 v, double4 xr, double fx, double fy, double fz,
-                                         double4* __restrict__ pos_out) {
+__device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, const RepDev& rp,
+                                         int64_t i, double4 pi, double4 v, double4 xr, double fx,
+                                         double fy, double fz, double4* __restrict__ pos_out) {
   const double k = g.dt * g.acc;
   v.x = fma(k, fx, v.x);
   v.y = fma(k, fy, v.y);
@@ -818,6 +866,9 @@ __device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, int6
   xn.z = fma(g.dt, v.z, pi.z);
   xn.w = 0.0;
   pos_out[i] = xn;
+  // the mixed form's record goes with the position (pos_out is always the
+  // other buffer of s)
+  if (s.rec) s.rec_alt[i] = pos_record(rp, xn.x, xn.y, xn.z);
   s.vel[i] = v;
   const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
   const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
@@ -858,7 +909,7 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_integrate(
     double fx, fy, fz;
     pair_forces<PREC, LPA>(g, s, t, rp, pos_in, lds_d4, i, active, w.sub, pi, fx, fy, fz);
     bool far = false;
-    if (active && w.sub == 0) far = leapfrog(g, s, i, pi, v, xr, fx, fy, fz, pos_out);
+    if (active && w.sub == 0) far = leapfrog(g, s, rp, i, pi, v, xr, fx, fy, fz, pos_out);
     // one wave covers atoms of one tile, hence of one replica
     if (__ballot(far) != 0ull && lane_id() == 0) {
       *flag_next = 1;
@@ -974,7 +1025,7 @@ __device__ __forceinline__ bool force_tile(const Geometry& g, const State& s, co
   bool far = false;
   if (active && sub == 0) {
     if (pos_out) {
-      far = leapfrog(g, s, i, pi, v, xr, fx, fy, fz, pos_out);
+      far = leapfrog(g, s, g.reps[tl.rep], i, pi, v, xr, fx, fy, fz, pos_out);
     } else {
       s.frc[i] = make_double4(fx, fy, fz, 0.0);
       if (!isfinite(fx + fy + fz)) set_bits(s.status, ST_NONFINITE);
@@ -1138,7 +1189,8 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
         const bool active = w.a < tl.count;
         const RepDev& rp = g.reps[tl.rep];
         const int64_t i = tl.begin + (active ? w.a : 0);
-        const double rho_i = density_of<PREC, LPA>(g, s, t, rp, s.pos, dens_tab, i, active, w.sub);
+        const double rho_i =
+            density_of<PREC, LPA>(g, s, t, rp, s.pos, dens_tab, i, active, w.sub);
         if (!active || w.sub != 0) continue;
         store_fprime<PREC>(s, t, s.pos, i, rho_i, 0);
       }
@@ -1164,7 +1216,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
         double fx, fy, fz;
         pair_forces<PREC, LPA>(g, s, t, rp, s.pos, lds_d4, i, active, w.sub, pi, fx, fy, fz);
         bool far = false;
-        if (active && w.sub == 0) far = leapfrog(g, s, i, pi, v, xr, fx, fy, fz, s.pos_alt);
+        if (active && w.sub == 0) far = leapfrog(g, s, rp, i, pi, v, xr, fx, fy, fz, s.pos_alt);
         if (__ballot(far) != 0ull && lane_id() == 0) {
           *fl_nxt = 1;
           rf_nxt[tl.rep] = 1;
@@ -1301,9 +1353,11 @@ __global__ __launch_bounds__(256) void k_snapshot(State s, int64_t n, double4* _
     if (restore) {
       s.pos[k] = sp[k];
       s.vel[k] = sv[k];
+      if (s.rec) s.rec[k] = s.snap_rec[k];
     } else {
       sp[k] = s.pos[k];
       sv[k] = s.vel[k];
+      if (s.rec) s.snap_rec[k] = s.rec[k];
     }
   }
 }
