@@ -396,6 +396,22 @@ md_status md_fm_forward(md_fm_ctx* ctx, const double* coef_phi, const double* co
 md_status md_fm_backward(md_fm_ctx* ctx, double seed, double* g_phi, double* g_rho,
                          double* g_emb);
 
+/* The same two calls without a host synchronisation, for loops that need
+ * neither the loss nor the status on the host every evaluation (an optimiser
+ * on the device).  forward_async writes the loss to loss_dev (device double);
+ * backward_async reads its seed from seed_dev (device double).  Non-finite
+ * values and fixed-point overflows stay latched on the device until
+ * md_fm_check, which synchronises the context's stream, returns MD_OK or
+ * MD_E_NONFINITE for every call since the last check, and clears the latch
+ * (md_fm_forward also clears it first).  Launch order on the context's stream
+ * is the only ordering: a gradient array must not be read before the stream
+ * has run the backward call that writes it. */
+md_status md_fm_forward_async(md_fm_ctx* ctx, const double* coef_phi, const double* coef_rho,
+                              const double* coef_emb, double* loss_dev, double* f_out);
+md_status md_fm_backward_async(md_fm_ctx* ctx, const double* seed_dev, double* g_phi,
+                               double* g_rho, double* g_emb);
+md_status md_fm_check(md_fm_ctx* ctx);
+
 void md_fm_destroy(md_fm_ctx* ctx);
 
 #ifdef __cplusplus

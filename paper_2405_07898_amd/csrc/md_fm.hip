@@ -209,7 +209,7 @@ __global__ __launch_bounds__(64) void k_fm_force(FmArgs a) {
   if (threadIdx.x == 0) a.partial[blockIdx.x] = s_l[0];
 }
 
-__global__ __launch_bounds__(256) void k_fm_loss_reduce(FmArgs a) {
+__global__ __launch_bounds__(256) void k_fm_loss_reduce(FmArgs a, double* __restrict__ out) {
   __shared__ double s_l[256];
   double l = 0.0;
   for (int b = threadIdx.x; b < a.g.n_atiles; b += 256) l += a.partial[b];
@@ -219,7 +219,10 @@ __global__ __launch_bounds__(256) void k_fm_loss_reduce(FmArgs a) {
     if ((int)threadIdx.x < o) s_l[threadIdx.x] += s_l[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *a.loss = s_l[0];
+  if (threadIdx.x == 0) {
+    *a.loss = s_l[0];
+    if (out) *out = s_l[0];
+  }
 }
 
 // lambda_i = sum_j (g_i - g_j) . u_ij rho'(r_ij),  mu_i = lambda_i F''(rho_i),
@@ -416,11 +419,13 @@ __global__ __launch_bounds__(256) void k_fm_coef_reduce1(FmArgs a, int nblocks) 
                                            s_acc[3][lane];
 }
 
-__global__ __launch_bounds__(256) void k_fm_coef_reduce(FmArgs a, double seed, double* gp,
-                                                        double* gr, double* ge) {
+__global__ __launch_bounds__(256) void k_fm_coef_reduce(FmArgs a, double seed,
+                                                        const double* __restrict__ seed_dev,
+                                                        double* gp, double* gr, double* ge) {
   const int nb = a.nb_phi + a.nb_rho + a.nb_emb;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
+  if (seed_dev) seed = *seed_dev;
   unsigned long long acc = 0ull;
   for (int k = 0; k < kFmSplit; ++k) acc += a.part[(int64_t)k * nb + b];
   const double v = seed * ((double)(long long)acc * a.scale[1]);
@@ -636,38 +641,31 @@ md_status md_fm_create(md_fm_ctx** out, int32_t n_cfg, const int64_t* cfg_atoms,
   return MD_OK;
 }
 
-md_status md_fm_forward(md_fm_ctx* c, const double* coef_phi, const double* coef_rho,
-                        const double* coef_emb, double* loss, double* f_out) {
-  if (!c || !coef_phi || !coef_rho || !coef_emb) return MD_E_ARG;
+// The passes of one forward evaluation (no host synchronisation).
+static md_status fm_forward_launch(md_fm_ctx* c, const double* coef_phi, const double* coef_rho,
+                                   const double* coef_emb, double* loss_dev, double* f_out) {
   FmArgs& a = c->a;
   a.phi.coef = coef_phi;
   a.rho.coef = coef_rho;
   a.emb.coef = coef_emb;
   const int tb = c->v.L.atile_blocks;
-  FMC(c, hipMemsetAsync(a.flag, 0, sizeof(int32_t), c->stream));
   hipLaunchKernelGGL(k_fm_density, dim3(tb), dim3(64), 0, c->stream, a);
   FMC(c, hipGetLastError());
   hipLaunchKernelGGL(k_fm_force, dim3(tb), dim3(64), 0, c->stream, a);
   FMC(c, hipGetLastError());
-  hipLaunchKernelGGL(k_fm_loss_reduce, dim3(1), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_fm_loss_reduce, dim3(1), dim3(256), 0, c->stream, a, loss_dev);
   FMC(c, hipGetLastError());
   if (f_out) {
     hipLaunchKernelGGL(k_fm_export_f, dim3(tb), dim3(64), 0, c->stream, a, f_out);
     FMC(c, hipGetLastError());
   }
-  FMC(c, hipMemcpyAsync(c->host, a.loss, sizeof(double) + sizeof(int32_t),
-                        hipMemcpyDeviceToHost, c->stream));
-  FMC(c, hipStreamSynchronize(c->stream));
-  int32_t flag = 0;
-  memcpy(&flag, c->host + 1, sizeof(int32_t));
-  if (loss) *loss = c->host[0];
   c->have_forward = true;
-  return flag ? MD_E_NONFINITE : MD_OK;
+  return MD_OK;
 }
 
-md_status md_fm_backward(md_fm_ctx* c, double seed, double* g_phi, double* g_rho, double* g_emb) {
-  if (!c || !g_phi || !g_rho || !g_emb) return MD_E_ARG;
-  if (!c->have_forward) return MD_E_ORDER;
+// The passes of one backward evaluation (no host synchronisation).
+static md_status fm_backward_launch(md_fm_ctx* c, double seed, const double* seed_dev,
+                                    double* g_phi, double* g_rho, double* g_emb) {
   FmArgs& a = c->a;
   const int tb = c->v.L.atile_blocks;
   const int nb = a.nb_phi + a.nb_rho + a.nb_emb;
@@ -683,13 +681,63 @@ md_status md_fm_backward(md_fm_ctx* c, double seed, double* g_phi, double* g_rho
                      a, kFmBlocks);
   FMC(c, hipGetLastError());
   hipLaunchKernelGGL(k_fm_coef_reduce, dim3((nb + 255) / 256), dim3(256), 0, c->stream, a, seed,
-                     g_phi, g_rho, g_emb);
+                     seed_dev, g_phi, g_rho, g_emb);
   FMC(c, hipGetLastError());
-  FMC(c, hipMemcpyAsync(c->host + 1, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  return MD_OK;
+}
+
+// The flag word (non-finite values or fixed-point overflow latched by the
+// kernels) to the host, then cleared.
+static md_status fm_take_flag(md_fm_ctx* c, bool with_loss) {
+  FmArgs& a = c->a;
+  if (with_loss)
+    FMC(c, hipMemcpyAsync(c->host, a.loss, sizeof(double) + sizeof(int32_t),
+                          hipMemcpyDeviceToHost, c->stream));
+  else
+    FMC(c, hipMemcpyAsync(c->host + 1, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          c->stream));
+  FMC(c, hipMemsetAsync(a.flag, 0, sizeof(int32_t), c->stream));
   FMC(c, hipStreamSynchronize(c->stream));
   int32_t flag = 0;
   memcpy(&flag, c->host + 1, sizeof(int32_t));
   return flag ? MD_E_NONFINITE : MD_OK;
+}
+
+md_status md_fm_forward(md_fm_ctx* c, const double* coef_phi, const double* coef_rho,
+                        const double* coef_emb, double* loss, double* f_out) {
+  if (!c || !coef_phi || !coef_rho || !coef_emb) return MD_E_ARG;
+  FMC(c, hipMemsetAsync(c->a.flag, 0, sizeof(int32_t), c->stream));
+  md_status rc = fm_forward_launch(c, coef_phi, coef_rho, coef_emb, nullptr, f_out);
+  if (rc != MD_OK) return rc;
+  rc = fm_take_flag(c, true);
+  if (loss) *loss = c->host[0];
+  return rc;
+}
+
+md_status md_fm_backward(md_fm_ctx* c, double seed, double* g_phi, double* g_rho, double* g_emb) {
+  if (!c || !g_phi || !g_rho || !g_emb) return MD_E_ARG;
+  if (!c->have_forward) return MD_E_ORDER;
+  const md_status rc = fm_backward_launch(c, seed, nullptr, g_phi, g_rho, g_emb);
+  if (rc != MD_OK) return rc;
+  return fm_take_flag(c, false);
+}
+
+md_status md_fm_forward_async(md_fm_ctx* c, const double* coef_phi, const double* coef_rho,
+                              const double* coef_emb, double* loss_dev, double* f_out) {
+  if (!c || !coef_phi || !coef_rho || !coef_emb || !loss_dev) return MD_E_ARG;
+  return fm_forward_launch(c, coef_phi, coef_rho, coef_emb, loss_dev, f_out);
+}
+
+md_status md_fm_backward_async(md_fm_ctx* c, const double* seed_dev, double* g_phi,
+                               double* g_rho, double* g_emb) {
+  if (!c || !seed_dev || !g_phi || !g_rho || !g_emb) return MD_E_ARG;
+  if (!c->have_forward) return MD_E_ORDER;
+  return fm_backward_launch(c, 0.0, seed_dev, g_phi, g_rho, g_emb);
+}
+
+md_status md_fm_check(md_fm_ctx* c) {
+  if (!c) return MD_E_ARG;
+  return fm_take_flag(c, false);
 }
 
 void md_fm_destroy(md_fm_ctx* c) {

@@ -82,6 +82,42 @@ class ForceMatch:
         _md._check(rc, "md_fm_backward")
         return gs
 
+    def forward_async(self, coef_phi, coef_rho, coef_emb, want_forces: bool = False):
+        """The loss as a device tensor, with no host synchronisation; errors stay
+        latched until check()."""
+        t = self.torch
+        cs = [self._dev(c).contiguous() for c in (coef_phi, coef_rho, coef_emb)]
+        for c, shp in zip(cs, self.shapes):
+            if tuple(c.shape) != tuple(shp):
+                raise ValueError(f"coefficient shape {tuple(c.shape)} != {tuple(shp)}")
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        f = t.empty((self.n, 3), dtype=t.float64, device=self.device) if want_forces else None
+        loss = t.empty((), dtype=t.float64, device=self.device)
+        _md._check(_md.lib().md_fm_forward_async(
+            self.ctx, *[C.c_void_p(c.data_ptr()) for c in cs], C.c_void_p(loss.data_ptr()),
+            C.c_void_p(f.data_ptr()) if f is not None else None), "md_fm_forward_async")
+        self._last = cs
+        t.cuda.current_stream(self.device).wait_stream(self.stream)
+        return loss, f
+
+    def backward_async(self, seed):
+        """Gradients for the last forward, scaled by the device scalar `seed`,
+        with no host synchronisation."""
+        t = self.torch
+        seed = self._dev(seed).reshape(())
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        gs = [t.empty(shp, dtype=t.float64, device=self.device) for shp in self.shapes]
+        _md._check(_md.lib().md_fm_backward_async(self.ctx, C.c_void_p(seed.data_ptr()),
+                                                  *[C.c_void_p(g.data_ptr()) for g in gs]),
+                   "md_fm_backward_async")
+        self._seed = seed  # alive until the stream has read it
+        t.cuda.current_stream(self.device).wait_stream(self.stream)
+        return gs
+
+    def check(self):
+        """Raises if any call since the last check met a non-finite value."""
+        _md._check(_md.lib().md_fm_check(self.ctx), "md_fm_check")
+
     def close(self):
         if getattr(self, "ctx", None):
             self.stream.synchronize()
@@ -103,18 +139,21 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, coef_phi, coef_rho, coef_emb, problem):
-            loss, _ = problem.forward(coef_phi.detach(), coef_rho.detach(), coef_emb.detach())
+            # no host synchronisation: the loss stays on the device, and errors
+            # stay latched until problem.check()
+            loss, _ = problem.forward_async(coef_phi.detach(), coef_rho.detach(),
+                                            coef_emb.detach())
             ctx.problem = problem
             ctx.coefs = (coef_phi.detach(), coef_rho.detach(), coef_emb.detach())
-            return torch.tensor(loss, dtype=torch.float64, device=coef_phi.device)
+            return loss
 
         @staticmethod
         def backward(ctx, grad_loss):
             p = ctx.problem
             # the adjoint needs the forward state of these coefficients
             if p._last is None or any(a.data_ptr() != b.data_ptr() for a, b in zip(p._last, ctx.coefs)):
-                p.forward(*ctx.coefs)
-            g = p.backward(float(grad_loss))
+                p.forward_async(*ctx.coefs)
+            g = p.backward_async(grad_loss.detach())
             return g[0], g[1], g[2], None
 
     return EamForceMatch

@@ -64,6 +64,7 @@ EXPORTED = [
     "md_get_replica_schedule", "md_autotune", "md_last_error",
     "md_status_string", "md_destroy", "md_create_multi", "md_set_types",
     "md_fm_workspace_size", "md_fm_create", "md_fm_forward", "md_fm_backward", "md_fm_destroy",
+    "md_fm_forward_async", "md_fm_backward_async", "md_fm_check",
     "md_forces_static",
 ]
 
@@ -112,6 +113,9 @@ def lib():
                                    P(md_spline), vp, vp, vp, sz, vp]),
             "md_fm_forward": (i32, [vp, vp, vp, vp, P(d), vp]),
             "md_fm_backward": (i32, [vp, d, vp, vp, vp]),
+            "md_fm_forward_async": (i32, [vp, vp, vp, vp, vp, vp]),
+            "md_fm_backward_async": (i32, [vp, vp, vp, vp, vp]),
+            "md_fm_check": (i32, [vp]),
             "md_fm_destroy": (None, [vp]),
             "md_forces_static": (i32, [P(md_params), i64, P(d), P(md_spline), P(md_spline),
                                        P(md_spline), vp, vp, vp, vp, vp]),

@@ -114,3 +114,39 @@ def test_adjoint_is_deterministic_and_autograd_consistent(fm, oracle_lib):
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - flat[q]) <= tol + 1e-9 * np.max(np.abs(flat)), (which, q, fd, flat[q])
     prob.close()
+
+
+def test_async_calls_equal_the_synchronous_ones(fm, oracle_lib):
+    """md_fm_forward_async / md_fm_backward_async (no host synchronisation, the
+    loss and the seed on the device) give bitwise the loss and gradients of
+    the synchronous calls; a non-finite evaluation stays latched until
+    md_fm_check, which reports it once and clears it."""
+    import torch
+
+    from paper_2405_07898_amd import md
+
+    boxes = configs.config_fm(3, 5)
+    x, off, bx, fref = _problem(oracle_lib, boxes)
+    tabs = P.fm_tables()
+    _say(f"[gpu] force matching async calls n={x.shape[0]}")
+    prob = fm.ForceMatch(x, fref, np.diff(off), bx, tabs)
+    coefs = [torch.as_tensor(t.coef, device="cuda") for t in tabs]
+    loss_s, _ = prob.forward(*coefs)
+    g_s = [t.cpu().numpy() for t in prob.backward(0.5)]
+    loss_a, _ = prob.forward_async(*coefs)
+    g_a = [t.cpu().numpy() for t in prob.backward_async(torch.tensor(0.5, dtype=torch.float64))]
+    prob.check()
+    assert loss_a.item() == loss_s
+    for a, b in zip(g_a, g_s):
+        assert np.array_equal(a, b)
+    bad = [c.clone() for c in coefs]
+    bad[0].fill_(float("nan"))  # every phi segment, so the visited ones too
+    prob.forward_async(*bad)
+    prob.backward_async(torch.tensor(1.0, dtype=torch.float64))
+    with pytest.raises(md.MDError) as err:
+        prob.check()
+    assert err.value.code == md.MD_E_NONFINITE
+    prob.check()  # cleared
+    loss_b, _ = prob.forward(*coefs)
+    assert loss_b == loss_s
+    prob.close()
