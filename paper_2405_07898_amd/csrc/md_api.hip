@@ -144,6 +144,7 @@ struct md_ctx {
   };
   std::vector<Tail> tails;
   int persist_cap = 0;  // most co-resident workgroups of the persistent kernel
+  int binbuild_grid = 0;  // workgroups of the fused bin + build launch (0: two launches)
   std::string err;
 };
 
@@ -456,8 +457,12 @@ md_status step_eager(md_ctx* c) {
   int32_t* fl_nxt = c->status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
   int32_t* rf_cur = s.rflag + (k == 0 ? 0 : c->n_rep);
   int32_t* rf_nxt = s.rflag + (k == 0 ? c->n_rep : 0);
-  HIPC(c, launch_bin(c->L, c->g, s, fl_cur, rf_cur));
-  HIPC(c, launch_build(c->L, c->g, s, fl_cur, rf_cur));
+  if (c->binbuild_grid) {
+    HIPC(c, launch_binbuild(c->L, c->g, s, fl_cur, rf_cur, c->binbuild_grid));
+  } else {
+    HIPC(c, launch_bin(c->L, c->g, s, fl_cur, rf_cur));
+    HIPC(c, launch_build(c->L, c->g, s, fl_cur, rf_cur));
+  }
   HIPC(c, density_pass(c, s, c->lpa, s.pos, fl_cur, fl_nxt, rf_nxt, false));
   HIPC(c, force_integrate_pass(c, s, c->lpa, s.pos, c->st[1 - k].pos, fl_nxt, rf_nxt));
   c->cur = 1 - k;
@@ -849,6 +854,17 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
       c->persist_cap = (c->L.persist_blocks / kXcd) * kXcd;
     }
     if (e2 == hipSuccess && p->list_mode == MD_LIST_HALF) e2 = allow_half_lds(t);
+    // small systems: binning and list build of each step in one launch (a
+    // grid barrier between them), if every workgroup it needs fits at once
+    if (e2 == hipSuccess && p->list_mode == MD_LIST_FULL &&
+        binbuild_lds_bytes(p->cell_capacity) <= 65536) {
+      const int64_t waves = std::max<int64_t>(ls.ctile_blocks, ls.atile_blocks);
+      int64_t grid = (waves + kPersistThreads / 64 - 1) / (kPersistThreads / 64);
+      grid = (std::max<int64_t>(grid, kXcd) + kXcd - 1) / kXcd * kXcd;
+      const int per_cu = binbuild_blocks_per_cu(p->cell_capacity);
+      if (grid <= kMaxBinbuildGrid && grid <= (int64_t)per_cu * cus)
+        c->binbuild_grid = (int)grid;
+    }
     if (e2 != hipSuccess) {
       md_status r_ = hip_fail(c, e2, "hipFuncSetAttribute");
       delete c;
@@ -1127,6 +1143,8 @@ md_status md_step(md_ctx* c, int64_t n) {
     // and rebuild the list there
     c->cur = 0;
     HIPC(c, hipMemsetAsync(c->status + SW_BITS, 0, sizeof(int32_t), c->L.stream));
+    // a barrier left by a stalled launch starts again from no arrivals
+    HIPC(c, hipMemsetAsync(c->status + SW_BAR_COUNT, 0, 3 * sizeof(int32_t), c->L.stream));
     HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, true));
     md_status r = rebuild_sorted(c, true);
     if (r == MD_OK) r = forces_now(c, false);

@@ -20,6 +20,7 @@ constexpr uint32_t kNoShift = 21u;   // code of the zero image shift: 1 | 1<<2 |
 constexpr int kXcd = 8;              // MI355X dispatches workgroups round-robin over 8 XCDs
 constexpr int kMaxTypes = 4;         // atom types of the multi-species form
 constexpr int kPersistThreads = 512; // threads per workgroup of the persistent step kernel
+constexpr int kMaxBinbuildGrid = 64;  // largest grid of the fused bin + build launch (its barrier's cost grows with it)
 
 // status word bits (device, sticky)
 constexpr int32_t ST_NBR_OVERFLOW = 1;
@@ -215,6 +216,12 @@ hipError_t launch_zero_bins(const Launch& L, const State& s, int64_t n_cells_tot
 hipError_t launch_cell_stats(const Launch& L, const State& s, int64_t n_cells_total);
 hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                       const int32_t* rcond);
+// Binning and list build in one launch with a grid barrier (small systems);
+// grid at most binbuild_blocks_per_cu() x compute units.
+hipError_t launch_binbuild(const Launch& L, const Geometry& g, const State& s,
+                           const int32_t* cond, const int32_t* rcond, int grid);
+size_t binbuild_lds_bytes(int cell_cap);
+int binbuild_blocks_per_cu(int cell_cap);
 hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                         const int32_t* rcond);
 hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64_t n_cells_total);

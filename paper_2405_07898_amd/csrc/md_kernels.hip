@@ -1227,6 +1227,65 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
   }
 }
 
+// Binning and list build of a rebuild-check step in one launch, for systems
+// small enough that a grid barrier between the two phases is cheaper than a
+// second graph node (a graph node costs a few microseconds even when it only
+// finds no rebuild due, and in most steps none is).  Phases and barrier are
+// those of k_persist: the same device code, so the list is bitwise that of
+// k_bin + k_build.  The grid never exceeds the workgroups that fit on the chip
+// at once (checked when the context is created), and the barrier's wait is
+// bounded.
+__global__ __launch_bounds__(kPersistThreads) void k_binbuild(Geometry g, State s,
+                                                              const int32_t* cond,
+                                                              const int32_t* rcond) {
+  // the rebuild flag is written only by earlier kernels, so every workgroup
+  // reads the same value: all leave here, or none
+  const int32_t due = cond ? *cond : 1;
+  if (due == 0) return;
+  // the status word is not: an error raised by the binning of one workgroup
+  // may or may not be seen by another at its start.  Every workgroup reaches
+  // the barrier, whose last arrival decides for all whether to go on.
+  const bool err = has_error(s.status);
+  extern __shared__ double4 lds_d4[];
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int nwaves = (int)blockDim.x >> 6;
+  const size_t bl = (build_lds_bytes(g.cell_cap) + 15) & ~size_t(15);
+  const BuildLds L = carve_build_lds(reinterpret_cast<char*>(lds_d4) + (size_t)wave * bl,
+                                     g.cell_cap);
+  if (cond && !err && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
+  const int64_t gstride = (int64_t)gridDim.x * nwaves;
+  const int64_t gwave = (int64_t)blockIdx.x * nwaves + wave;
+  if (!err)
+    for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rcond, lane);
+  if (!grid_sync(s.status)) return;
+  for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
+    const CellTile ct = g.ctiles[b];
+    if (ct.cell < 0 || (rcond && rcond[ct.rep] == 0)) continue;
+    build_cell<true>(g, s, ct, L, lane);
+    build_sync<true>();  // the wave's next cell reuses its staging arrays
+  }
+}
+
+size_t binbuild_lds_bytes(int cell_cap) {
+  return (size_t)(kPersistThreads / 64) * ((build_lds_bytes(cell_cap) + 15) & ~size_t(15));
+}
+
+int binbuild_blocks_per_cu(int cell_cap) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_binbuild),
+                                                   kPersistThreads,
+                                                   binbuild_lds_bytes(cell_cap)) != hipSuccess)
+    return 0;
+  return n;
+}
+
+hipError_t launch_binbuild(const Launch& L, const Geometry& g, const State& s,
+                           const int32_t* cond, const int32_t* rcond, int grid) {
+  hipLaunchKernelGGL(k_binbuild, dim3(grid), dim3(kPersistThreads),
+                     binbuild_lds_bytes(g.cell_cap), L.stream, g, s, cond, rcond);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(64) void k_halfkick(Geometry g, State s, double coef) {
   const AtomTile tl = g.atiles[blockIdx.x];
   if ((int)threadIdx.x >= tl.count) return;
