@@ -144,7 +144,7 @@ struct md_ctx {
   };
   std::vector<Tail> tails;
   int persist_cap = 0;  // most co-resident workgroups of the persistent kernel
-  int binbuild_grid = 0;  // workgroups of the fused bin + build launch (0: two launches)
+  int binbuild_grid = 0;  // workgroups of the fused bin + build + density launch (0: three launches)
   std::string err;
 };
 
@@ -358,7 +358,7 @@ md_status read_status(md_ctx* c, int32_t* words) {
 }
 
 md_status status_code(int32_t bits) {
-  if (bits & ST_STALL) return MD_E_STALL;
+  if (bits & (ST_STALL | ST_PLACEMENT)) return MD_E_STALL;
   if (bits & ST_NBR_OVERFLOW) return MD_E_NBR_OVERFLOW;
   if (bits & ST_CELL_OVERFLOW) return MD_E_CELL_OVERFLOW;
   if (bits & ST_LOST) return MD_E_LOST_ATOM;
@@ -436,11 +436,25 @@ md_status forces_now(md_ctx* c, bool want_rho) {
   return MD_OK;
 }
 
-// Workgroups of the persistent launch: enough that each takes about one tile
-// per pass (a tile = 64 atoms, 8 / lanes_per_atom tiles per workgroup
-// iteration), at least 8 and at most 64 (a barrier's cost grows with the
-// count) and never more than can be resident; a multiple of the XCD count.
+// Whether the persistent launch runs the small-system kernel: its atom tiles
+// fit one thread slot each on the workgroups of one XCD (a workgroup takes
+// 8 / lanes_per_atom tiles of 64 atoms at once), at most one XCD's share of
+// the resident workgroups.
+int64_t persist_small_blocks(const md_ctx* c) {
+  const int per = std::max(1, (kPersistThreads / 64) / c->lpa);
+  const int64_t need = (c->g.n_atiles + per - 1) / per;
+  const int64_t fit = std::min<int64_t>(std::max(c->persist_cap, kXcd) / kXcd, kMaxSlots);
+  return need <= fit ? need : 0;
+}
+
+// Workgroups of the persistent launch.  The small-system kernel asks for eight
+// times the workgroups it wants working, since only those that run on XCD 0
+// take part (workgroups go round-robin over the eight XCDs).  Otherwise:
+// enough that each takes about one tile per pass, at least 8 and at most 64 (a
+// barrier's cost grows with the count) and never more than can be resident; a
+// multiple of the XCD count.
 int persist_grid(const md_ctx* c) {
+  if (const int64_t w = persist_small_blocks(c)) return (int)(w * kXcd);
   const int64_t tiles = (c->sz.n + 63) / 64 + c->n_rep;
   const int per = std::max(1, (kPersistThreads / 64) / c->lpa);
   int64_t g = (tiles + per - 1) / per;
@@ -457,13 +471,14 @@ md_status step_eager(md_ctx* c) {
   int32_t* fl_nxt = c->status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
   int32_t* rf_cur = s.rflag + (k == 0 ? 0 : c->n_rep);
   int32_t* rf_nxt = s.rflag + (k == 0 ? c->n_rep : 0);
-  if (c->binbuild_grid) {
-    HIPC(c, launch_binbuild(c->L, c->g, s, fl_cur, rf_cur, c->binbuild_grid));
+  if (c->binbuild_grid && c->lpa > 0 && !c->multi && !c->half) {
+    HIPC(c, launch_bin_build_density(c->L, c->g, s, c->t, c->p.precision, c->lpa, fl_cur, rf_cur,
+                                     fl_nxt, rf_nxt, c->sz.cells, c->binbuild_grid));
   } else {
     HIPC(c, launch_bin(c->L, c->g, s, fl_cur, rf_cur));
     HIPC(c, launch_build(c->L, c->g, s, fl_cur, rf_cur));
+    HIPC(c, density_pass(c, s, c->lpa, s.pos, fl_cur, fl_nxt, rf_nxt, false));
   }
-  HIPC(c, density_pass(c, s, c->lpa, s.pos, fl_cur, fl_nxt, rf_nxt, false));
   HIPC(c, force_integrate_pass(c, s, c->lpa, s.pos, c->st[1 - k].pos, fl_nxt, rf_nxt));
   c->cur = 1 - k;
   return MD_OK;
@@ -597,7 +612,9 @@ const char* md_status_string(md_status s) {
     case MD_E_HIP: return "HIP runtime error";
     case MD_E_ORDER: return "call out of order";
     case MD_E_LOST_ATOM: return "atom moved more than one box length";
-    case MD_E_STALL: return "a grid barrier of a persistent launch timed out";
+    case MD_E_STALL:
+      return "a grid barrier of a persistent launch timed out, or too few of its workgroups ran on "
+             "the XCD that a one-XCD launch works on";
     case MD_E_WORKSPACE: return "workspace too small or misaligned";
     case MD_W_RHO_RANGE: return "warning: density beyond the embedding table";
     default: return "unknown status";
@@ -854,16 +871,18 @@ md_status create_impl(md_ctx** out, const md_params* p, int32_t n_rep, const int
       c->persist_cap = (c->L.persist_blocks / kXcd) * kXcd;
     }
     if (e2 == hipSuccess && p->list_mode == MD_LIST_HALF) e2 = allow_half_lds(t);
-    // small systems: binning and list build of each step in one launch (a
-    // grid barrier between them), if every workgroup it needs fits at once
-    if (e2 == hipSuccess && p->list_mode == MD_LIST_FULL &&
-        binbuild_lds_bytes(p->cell_capacity) <= 65536) {
+    // small systems: binning, list build and density pass of each step in one
+    // launch (grid barriers between them), if every workgroup it needs fits at
+    // once; one species, full list
+    if (e2 == hipSuccess && p->list_mode == MD_LIST_FULL && !mi &&
+        bbd_lds_bytes(t, p->precision, p->cell_capacity) <= (size_t)lds_max) {
       const int64_t waves = std::max<int64_t>(ls.ctile_blocks, ls.atile_blocks);
       int64_t grid = (waves + kPersistThreads / 64 - 1) / (kPersistThreads / 64);
       grid = (std::max<int64_t>(grid, kXcd) + kXcd - 1) / kXcd * kXcd;
-      const int per_cu = binbuild_blocks_per_cu(p->cell_capacity);
-      if (grid <= kMaxBinbuildGrid && grid <= (int64_t)per_cu * cus)
-        c->binbuild_grid = (int)grid;
+      if (grid <= kMaxBinbuildGrid) {
+        const int per_cu = bbd_blocks_per_cu(t, p->precision, p->cell_capacity);
+        if (grid <= (int64_t)per_cu * cus) c->binbuild_grid = (int)grid;
+      }
     }
     if (e2 != hipSuccess) {
       md_status r_ = hip_fail(c, e2, "hipFuncSetAttribute");
@@ -1110,9 +1129,10 @@ md_status md_step(md_ctx* c, int64_t n) {
       }
       if (c->p.launch_mode == MD_LAUNCH_PERSISTENT) {
         HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, false));
-        HIPC(c, hipMemsetAsync(c->status + SW_BAR_COUNT, 0, 3 * sizeof(int32_t), c->L.stream));
+        HIPC(c, hipMemsetAsync(c->status + SW_BAR_COUNT, 0, (SW_WORDS - SW_BAR_COUNT) * sizeof(int32_t), c->L.stream));
         HIPC(c, launch_persist(c->L, c->g, c->st[0], c->st[1], c->t, c->p.precision, c->lpa,
-                               chunk, c->sz.cells, persist_grid(c)));
+                               chunk, c->sz.cells, persist_grid(c),
+                               persist_small_blocks(c) > 0 ? 1 : 0));
       } else {
         if ((s = capture_chunk(c)) != MD_OK) return s;
         HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, false));
@@ -1144,7 +1164,7 @@ md_status md_step(md_ctx* c, int64_t n) {
     c->cur = 0;
     HIPC(c, hipMemsetAsync(c->status + SW_BITS, 0, sizeof(int32_t), c->L.stream));
     // a barrier left by a stalled launch starts again from no arrivals
-    HIPC(c, hipMemsetAsync(c->status + SW_BAR_COUNT, 0, 3 * sizeof(int32_t), c->L.stream));
+    HIPC(c, hipMemsetAsync(c->status + SW_BAR_COUNT, 0, (SW_WORDS - SW_BAR_COUNT) * sizeof(int32_t), c->L.stream));
     HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, true));
     md_status r = rebuild_sorted(c, true);
     if (r == MD_OK) r = forces_now(c, false);

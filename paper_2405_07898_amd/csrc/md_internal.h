@@ -20,7 +20,8 @@ constexpr uint32_t kNoShift = 21u;   // code of the zero image shift: 1 | 1<<2 |
 constexpr int kXcd = 8;              // MI355X dispatches workgroups round-robin over 8 XCDs
 constexpr int kMaxTypes = 4;         // atom types of the multi-species form
 constexpr int kPersistThreads = 512; // threads per workgroup of the persistent step kernel
-constexpr int kMaxBinbuildGrid = 64;  // largest grid of the fused bin + build launch (its barrier's cost grows with it)
+constexpr int kMaxSlots = 64;        // participants of a one-XCD persistent launch (at most)
+constexpr int kMaxBinbuildGrid = 64;  // largest grid of the fused bin + build + density launch (its barrier's cost grows with it)
 
 // status word bits (device, sticky)
 constexpr int32_t ST_NBR_OVERFLOW = 1;
@@ -29,6 +30,7 @@ constexpr int32_t ST_NONFINITE = 4;
 constexpr int32_t ST_LOST = 8;
 constexpr int32_t ST_BAD_TYPE = 16;
 constexpr int32_t ST_STALL = 32;      // a grid barrier of the persistent launch timed out
+constexpr int32_t ST_PLACEMENT = 64;  // a one-XCD persistent launch found too few workgroups on XCD 0
 constexpr int32_t ST_ERR_MASK = 0xff;
 constexpr int32_t ST_RHO_RANGE = 256;
 
@@ -48,7 +50,9 @@ enum StatusWord : int {
   SW_BAR_COUNT = 20,   // grid barrier of the persistent launch: arrivals
   SW_BAR_GEN = 21,     //   generation
   SW_BAR_STOP = 22,    //   stop decision of the last arrival
-  SW_WORDS = 64
+  SW_XCD_TICKET = 23,  //   workgroups of a one-XCD persistent launch that found themselves on XCD 0
+  SW_SLOTS = 128,      //   arrival slots of its participants, two parities of kMaxSlots
+  SW_WORDS = 256
 };
 
 // ---------------------------------------------------------------- structs
@@ -218,10 +222,13 @@ hipError_t launch_bin(const Launch& L, const Geometry& g, const State& s, const 
                       const int32_t* rcond);
 // Binning and list build in one launch with a grid barrier (small systems);
 // grid at most binbuild_blocks_per_cu() x compute units.
-hipError_t launch_binbuild(const Launch& L, const Geometry& g, const State& s,
-                           const int32_t* cond, const int32_t* rcond, int grid);
-size_t binbuild_lds_bytes(int cell_cap);
-int binbuild_blocks_per_cu(int cell_cap);
+hipError_t launch_bin_build_density(const Launch& L, const Geometry& g, const State& s,
+                                    const Tables& t, int precision, int lpa,
+                                    const int32_t* cond, const int32_t* rcond,
+                                    int32_t* clear_flag, int32_t* rclear, int64_t ncells,
+                                    int grid);
+size_t bbd_lds_bytes(const Tables& t, int prec, int cell_cap);
+int bbd_blocks_per_cu(const Tables& t, int precision, int cell_cap);
 hipError_t launch_build(const Launch& L, const Geometry& g, const State& s, const int32_t* cond,
                         const int32_t* rcond);
 hipError_t launch_sort(const Launch& L, const Geometry& g, const State& s, int64_t n_cells_total);
@@ -287,7 +294,7 @@ hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, d
 // the state with position buffer 0 / 1 current (buffer 0 current at entry).
 hipError_t launch_persist(const Launch& L, const Geometry& g, const State& s0, const State& s1,
                           const Tables& t, int precision, int lpa, int32_t nsteps, int64_t ncells,
-                          int grid);
+                          int grid, int one_xcd);
 hipError_t allow_persist_lds(const Tables& t, int precision, int cell_cap);
 size_t persist_lds_bytes(const Tables& t, int precision, int cell_cap);
 hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,

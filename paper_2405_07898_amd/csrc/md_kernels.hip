@@ -589,34 +589,61 @@ __device__ __forceinline__ void lane_sum2(float& s, float& c) {
 // rho_i of one atom (its lane's share), table rows from LDS.  Each batch
 // loads kBatch list entries, then their positions, then table rows.
 
+// One list entry's density term: float64 from the gathered position (x, y
+// in qxy, z in qz), mixed from the fixed-point records.
+__device__ __forceinline__ void dens_term64(const Geometry& g, const Tables& t, const RepDev& rp,
+                                            const void* lds_tab, uint32_t e, bool v, double2 qxy,
+                                            double qz, double2 pxy, double pz, double& acc) {
+  double dx, dy, dz;
+  separation(e, rp, qxy.x, qxy.y, qz, pxy.x, pxy.y, pz, dx, dy, dz);
+  const double4* tab = reinterpret_cast<const double4*>(lds_tab);
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const bool in = v && r2 < g.rc2;
+  const double rr = in ? r2 : 1.0;
+  const double x = (rr * rsq64(rr)) * t.r_inv_dx;
+  const int kk = min(max((int)x, 0), t.nr - 2);
+  const double tt = x - (double)kk;
+  const double4 c = tab[kk];
+  if (in) acc += fma(fma(fma(c.w, tt, c.z), tt, c.y), tt, c.x);
+}
+
+__device__ __forceinline__ void dens_term32(const Geometry& g, const Tables& t, const RepDev& rp,
+                                            const void* lds_tab, bool v, uint4 qr, uint4 qi,
+                                            float& sum, float& comp) {
+  const float4* tab = reinterpret_cast<const float4*>(lds_tab);
+  // separation from the fixed-point records (int32 wrap-around gives the
+  // minimum image, the listed one for every list pair)
+  const float fx = (float)(int32_t)(qr.x - qi.x) * rp.qs[0];
+  const float fy = (float)(int32_t)(qr.y - qi.y) * rp.qs[1];
+  const float fz = (float)(int32_t)(qr.z - qi.z) * rp.qs[2];
+  const float r2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
+  const bool in = v && r2 < g.rc2f;
+  const float rr = in ? r2 : 1.0f;
+  const float x = (rr * __builtin_amdgcn_rsqf(rr)) * t.r_inv_dx32;
+  const int kk = min(max((int)x, 0), t.nr - 2);
+  const float tt = x - (float)kk;
+  const float4 c = tab[kk];
+  if (in) two_sum_acc(sum, comp, fmaf(fmaf(fmaf(c.w, tt, c.z), tt, c.y), tt, c.x));
+}
+
+// The list entries k0, k0 + LPA, ... (below m) of atom i's density sum, in
+// batches of kBatch entries, added to this lane's sum in list order.
 template <int PREC, int LPA>
-__device__ __forceinline__ double density_of(const Geometry& g, const State& s, const Tables& t,
+__device__ __forceinline__ void density_from(const Geometry& g, const State& s, const Tables& t,
                                              const RepDev& rp, const double4* __restrict__ pos,
-                                             const void* lds_tab, int64_t i, bool active,
-                                             int sub) {
+                                             const void* lds_tab, int64_t i, int k_first, int m,
+                                             double2 pxy, double pz, uint4 qi, double& acc,
+                                             float& sum, float& comp) {
   const uint32_t N = (uint32_t)g.n;
   const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
-  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-  double2 pxy = make_double2(0.0, 0.0);
-  double pz = 0.0;
-  uint4 qi = make_uint4(0u, 0u, 0u, 0u);
-  if (PREC == 0) {
-    pxy = *reinterpret_cast<const double2*>(&pos[i]);
-    pz = pos[i].z;
-  } else {
-    qi = s.rec[i];
-  }
-  const int last = t.nr - 2;
-  double acc = 0.0;
-  float sum = 0.0f, comp = 0.0f;
   const double2* __restrict__ pos2 = reinterpret_cast<const double2*>(pos);
   const double* __restrict__ posd = reinterpret_cast<const double*>(pos);
   // the next batch's list entries are requested before this batch's
   // positions are used, so the list latency hides behind the gather
   const int kstep = LPA * kBatch;
   uint32_t e[kBatch];
-  load_entries<LPA>(s.nbr, N, (uint32_t)i, sub, m, self_e, e);
-  for (int k0 = sub; k0 < m; k0 += kstep) {
+  load_entries<LPA>(s.nbr, N, (uint32_t)i, k_first, m, self_e, e);
+  for (int k0 = k_first; k0 < m; k0 += kstep) {
     double2 qxy[kBatch];
     double qz[kBatch];
     uint4 qr[kBatch];
@@ -635,63 +662,71 @@ __device__ __forceinline__ double density_of(const Geometry& g, const State& s, 
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const bool v = k0 + u * LPA < m;
-      if (PREC == 0) {
-        double dx, dy, dz;
-        separation(e[u], rp, qxy[u].x, qxy[u].y, qz[u], pxy.x, pxy.y, pz, dx, dy, dz);
-        const double4* tab = reinterpret_cast<const double4*>(lds_tab);
-        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const bool in = v && r2 < g.rc2;
-        const double rr = in ? r2 : 1.0;
-        const double x = (rr * rsq64(rr)) * t.r_inv_dx;
-        const int kk = min(max((int)x, 0), last);
-        const double tt = x - (double)kk;
-        const double4 c = tab[kk];
-        if (in) acc += fma(fma(fma(c.w, tt, c.z), tt, c.y), tt, c.x);
-      } else {
-        const float4* tab = reinterpret_cast<const float4*>(lds_tab);
-        // separation from the fixed-point records (int32 wrap-around gives the
-        // minimum image, the listed one for every list pair)
-        const float fx = (float)(int32_t)(qr[u].x - qi.x) * rp.qs[0];
-        const float fy = (float)(int32_t)(qr[u].y - qi.y) * rp.qs[1];
-        const float fz = (float)(int32_t)(qr[u].z - qi.z) * rp.qs[2];
-        const float r2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
-        const bool in = v && r2 < g.rc2f;
-        const float rr = in ? r2 : 1.0f;
-        const float x = (rr * __builtin_amdgcn_rsqf(rr)) * t.r_inv_dx32;
-        const int kk = min(max((int)x, 0), last);
-        const float tt = x - (float)kk;
-        const float4 c = tab[kk];
-        if (in) two_sum_acc(sum, comp, fmaf(fmaf(fmaf(c.w, tt, c.z), tt, c.y), tt, c.x));
-      }
+      if (PREC == 0) dens_term64(g, t, rp, lds_tab, e[u], v, qxy[u], qz[u], pxy, pz, acc);
+      else dens_term32(g, t, rp, lds_tab, v, qr[u], qi, sum, comp);
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) e[u] = en[u];
   }
+}
+
+template <int PREC, int LPA>
+__device__ __forceinline__ double density_end(double acc, float sum, float comp) {
   if (PREC == 0) return lane_sum_sym<LPA>(acc);
   lane_sum2<LPA>(sum, comp);
   return (double)sum + (double)comp;
 }
 
-// F'(rho_i) from the embedding table (float64 for both forms) into pos[i].w;
-// the mixed form also into its record's fourth word (float32), which the
-// force pass gathers with the fixed-point position.
+// rho_i of one atom (its lane's share), table rows from LDS.
+template <int PREC, int LPA>
+__device__ __forceinline__ double density_of(const Geometry& g, const State& s, const Tables& t,
+                                             const RepDev& rp, const double4* __restrict__ pos,
+                                             const void* lds_tab, int64_t i, bool active,
+                                             int sub) {
+  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+  double2 pxy = make_double2(0.0, 0.0);
+  double pz = 0.0;
+  uint4 qi = make_uint4(0u, 0u, 0u, 0u);
+  if (PREC == 0) {
+    pxy = *reinterpret_cast<const double2*>(&pos[i]);
+    pz = pos[i].z;
+  } else {
+    qi = s.rec[i];
+  }
+  double acc = 0.0;
+  float sum = 0.0f, comp = 0.0f;
+  density_from<PREC, LPA>(g, s, t, rp, pos, lds_tab, i, sub, m, pxy, pz, qi, acc, sum, comp);
+  return density_end<PREC, LPA>(acc, sum, comp);
+}
+
+// F'(rho_i) from the embedding table (float64 for both forms; the mixed form
+// rounds it to float32, the precision its force pass gathers).  Past the last
+// knot F continues along its end tangent: F' = F'(end); beyond_range is set
+// when rho_i passes the table's end.
 template <int PREC>
-__device__ __forceinline__ void store_fprime(const State& s, const Tables& t, double4* pos,
-                                             int64_t i, double rho_i, int want_rho) {
+__device__ __forceinline__ double fprime_of(const Tables& t, double rho_i, bool& beyond_range) {
   const double xe = (rho_i - t.e_x0) * t.e_inv_dx;
   const int le = t.ne - 2;
   const int ke = (xe >= (double)le) ? le : ((xe > 0.0) ? (int)xe : 0);
-  // past the last knot F continues along its end tangent: F' = F'(end)
   const double te = fmin(xe - (double)ke, 1.0);
   const double4 ce = t.emb_val[ke];
   double fp = fma(fma(3.0 * ce.w, te, 2.0 * ce.z), te, ce.y) * t.e_inv_dx;
-  if (PREC != 0) {
-    fp = (double)(float)fp;
-    s.rec[i].w = __float_as_uint((float)fp);
-  }
+  if (PREC != 0) fp = (double)(float)fp;
+  beyond_range = xe > (double)(t.ne - 1);
+  return fp;
+}
+
+// F'(rho_i) into pos[i].w; the mixed form also into its record's fourth word
+// (float32), which the force pass gathers with the fixed-point position.
+template <int PREC>
+__device__ __forceinline__ void store_fprime(const State& s, const Tables& t, double4* pos,
+                                             int64_t i, double rho_i, int want_rho) {
+  bool beyond = false;
+  const double fp = fprime_of<PREC>(t, rho_i, beyond);
+  if (PREC != 0) s.rec[i].w = __float_as_uint((float)fp);
   pos[i].w = fp;
   if (want_rho) s.rho[i] = rho_i;
-  if (xe > (double)(t.ne - 1)) set_bits(s.status, ST_RHO_RANGE);
+  if (beyond) set_bits(s.status, ST_RHO_RANGE);
 }
 
 // rho_i = sum_{j in list, r^2 < rc^2} rho(r_ij); F'_i stored in pos[i].w.
@@ -741,25 +776,84 @@ __global__ __launch_bounds__(768) void k_density(Geometry g, State s, Tables t,
 // F_i = sum_j [(F'_i + F'_j) rho'(r) + phi'(r)] (x_j - x_i)/r   (Eq. EAMforce),
 // derivative rows from LDS (float64: 3 double2 per segment; mixed: float4 +
 // float2 arrays).  Same batching as the density pass.
+
+// One list entry's force term: float64 from the gathered record q (position
+// and F'_j) and the atom's own pi (position and F'_i); mixed from the
+// fixed-point records, F'_i = fpi.
+__device__ __forceinline__ void force_term64(const Geometry& g, const Tables& t, const RepDev& rp,
+                                             const void* lds_tab, uint32_t e, bool v, double4 q,
+                                             double4 pi, double& ax, double& ay, double& az) {
+  double dx, dy, dz;
+  separation(e, rp, q.x, q.y, q.z, pi.x, pi.y, pi.z, dx, dy, dz);
+  const double2* tab = reinterpret_cast<const double2*>(lds_tab);
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const bool in = v && r2 < g.rc2;
+  const double rr = in ? r2 : 1.0;
+  const double rinv = rsq64(rr);
+  const double x = (rr * rinv) * t.r_inv_dx;
+  const int kk = min(max((int)x, 0), t.nr - 2);
+  const double tt = x - (double)kk;
+  const double2 r0 = tab[3 * kk], r1 = tab[3 * kk + 1], r2v = tab[3 * kk + 2];
+  // r0 = (rho'0, rho'1), r1 = (rho'2, phi'0), r2v = (phi'1, phi'2)
+  const double drho = fma(fma(r1.x, tt, r0.y), tt, r0.x);
+  const double dphi = fma(fma(r2v.y, tt, r2v.x), tt, r1.y);
+  const double sc = fma(pi.w + q.w, drho, dphi) * rinv;
+  if (in) {
+    ax = fma(sc, dx, ax);
+    ay = fma(sc, dy, ay);
+    az = fma(sc, dz, az);
+  }
+}
+
+struct MixedForce {
+  float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
+};
+
+__device__ __forceinline__ void force_term32(const Geometry& g, const Tables& t, const RepDev& rp,
+                                             const void* lds_tab, bool v, uint4 qr, uint4 qi,
+                                             float fpi, MixedForce& a) {
+  const float4* ta = reinterpret_cast<const float4*>(lds_tab);
+  const float2* tb = reinterpret_cast<const float2*>(ta + (t.nr - 1));
+  // separation from the fixed-point difference: int32 wrap-around gives
+  // the minimum image, which is the listed image for every list pair
+  const float ex = (float)(int32_t)(qr.x - qi.x) * rp.qs[0];
+  const float ey = (float)(int32_t)(qr.y - qi.y) * rp.qs[1];
+  const float ez = (float)(int32_t)(qr.z - qi.z) * rp.qs[2];
+  const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+  const bool in = v && r2 < g.rc2f;
+  const float rr = in ? r2 : 1.0f;
+  const float rinv = __builtin_amdgcn_rsqf(rr);
+  const float x = (rr * rinv) * t.r_inv_dx32;
+  const int kk = min(max((int)x, 0), t.nr - 2);
+  const float tt = x - (float)kk;
+  const float4 A = ta[kk];
+  const float2 B = tb[kk];
+  const float drho = fmaf(fmaf(A.z, tt, A.y), tt, A.x);
+  const float dphi = fmaf(fmaf(B.y, tt, B.x), tt, A.w);
+  const float sc = fmaf(fpi + __uint_as_float(qr.w), drho, dphi) * rinv;
+  if (in) {
+    two_sum_acc(a.sx, a.cx, sc * ex);
+    two_sum_acc(a.sy, a.cy, sc * ey);
+    two_sum_acc(a.sz, a.cz, sc * ez);
+  }
+}
+
+// The list entries k0, k0 + LPA, ... (below m) of atom i's force sum, in
+// batches, added to this lane's sums in list order.
 template <int PREC, int LPA>
-__device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, const Tables& t,
+__device__ __forceinline__ void forces_from(const Geometry& g, const State& s, const Tables& t,
                                             const RepDev& rp, const double4* __restrict__ pos,
-                                            const void* lds_tab, int64_t i, bool active, int sub,
-                                            double4 pi, double& fx, double& fy, double& fz) {
+                                            const void* lds_tab, int64_t i, int k_first, int m,
+                                            double4 pi, uint4 qi, double& ax, double& ay,
+                                            double& az, MixedForce& mf) {
   const uint32_t N = (uint32_t)g.n;
   const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
-  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
-  const int last = t.nr - 2;
-  double ax = 0.0, ay = 0.0, az = 0.0;
-  float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sz = 0.f, cz = 0.f;
-  // mixed form: the atom's own record (fixed-point position, F' in float32)
-  const uint4 qi = PREC == 0 ? make_uint4(0u, 0u, 0u, 0u) : s.rec[i];
   const float fpi = PREC == 0 ? 0.0f : __uint_as_float(qi.w);
   constexpr int kB = PREC == 0 ? kBatch : kBatchMixed;
   const int kstep = LPA * kB;
   uint32_t e[kB];
-  load_entries<LPA>(s.nbr, N, (uint32_t)i, sub, m, self_e, e);
-  for (int k0 = sub; k0 < m; k0 += kstep) {
+  load_entries<LPA>(s.nbr, N, (uint32_t)i, k_first, m, self_e, e);
+  for (int k0 = k_first; k0 < m; k0 += kstep) {
     double4 q[kB];
     uint4 qr[kB];
 #pragma unroll
@@ -772,69 +866,43 @@ __device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, c
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
       const bool v = k0 + u * LPA < m;
-      if (PREC == 0) {
-        double dx, dy, dz;
-        separation(e[u], rp, q[u].x, q[u].y, q[u].z, pi.x, pi.y, pi.z, dx, dy, dz);
-        const double2* tab = reinterpret_cast<const double2*>(lds_tab);
-        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const bool in = v && r2 < g.rc2;
-        const double rr = in ? r2 : 1.0;
-        const double rinv = rsq64(rr);
-        const double x = (rr * rinv) * t.r_inv_dx;
-        const int kk = min(max((int)x, 0), last);
-        const double tt = x - (double)kk;
-        const double2 r0 = tab[3 * kk], r1 = tab[3 * kk + 1], r2v = tab[3 * kk + 2];
-        // r0 = (rho'0, rho'1), r1 = (rho'2, phi'0), r2v = (phi'1, phi'2)
-        const double drho = fma(fma(r1.x, tt, r0.y), tt, r0.x);
-        const double dphi = fma(fma(r2v.y, tt, r2v.x), tt, r1.y);
-        const double sc = fma(pi.w + q[u].w, drho, dphi) * rinv;
-        if (in) {
-          ax = fma(sc, dx, ax);
-          ay = fma(sc, dy, ay);
-          az = fma(sc, dz, az);
-        }
-      } else {
-        const float4* ta = reinterpret_cast<const float4*>(lds_tab);
-        const float2* tb = reinterpret_cast<const float2*>(ta + (t.nr - 1));
-        // separation from the fixed-point difference: int32 wrap-around gives
-        // the minimum image, which is the listed image for every list pair
-        const float ex = (float)(int32_t)(qr[u].x - qi.x) * rp.qs[0];
-        const float ey = (float)(int32_t)(qr[u].y - qi.y) * rp.qs[1];
-        const float ez = (float)(int32_t)(qr[u].z - qi.z) * rp.qs[2];
-        const float r2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-        const bool in = v && r2 < g.rc2f;
-        const float rr = in ? r2 : 1.0f;
-        const float rinv = __builtin_amdgcn_rsqf(rr);
-        const float x = (rr * rinv) * t.r_inv_dx32;
-        const int kk = min(max((int)x, 0), last);
-        const float tt = x - (float)kk;
-        const float4 A = ta[kk];
-        const float2 B = tb[kk];
-        const float drho = fmaf(fmaf(A.z, tt, A.y), tt, A.x);
-        const float dphi = fmaf(fmaf(B.y, tt, B.x), tt, A.w);
-        const float sc = fmaf(fpi + __uint_as_float(qr[u].w), drho, dphi) * rinv;
-        if (in) {
-          two_sum_acc(sx, cx, sc * ex);
-          two_sum_acc(sy, cy, sc * ey);
-          two_sum_acc(sz, cz, sc * ez);
-        }
-      }
+      if (PREC == 0) force_term64(g, t, rp, lds_tab, e[u], v, q[u], pi, ax, ay, az);
+      else force_term32(g, t, rp, lds_tab, v, qr[u], qi, fpi, mf);
     }
 #pragma unroll
     for (int u = 0; u < kB; ++u) e[u] = en[u];
   }
+}
+
+template <int PREC, int LPA>
+__device__ __forceinline__ void forces_end(double ax, double ay, double az, MixedForce& mf,
+                                           double& fx, double& fy, double& fz) {
   if (PREC == 0) {
     fx = lane_sum_sym<LPA>(ax);
     fy = lane_sum_sym<LPA>(ay);
     fz = lane_sum_sym<LPA>(az);
   } else {
-    lane_sum2<LPA>(sx, cx);
-    lane_sum2<LPA>(sy, cy);
-    lane_sum2<LPA>(sz, cz);
-    fx = (double)sx + (double)cx;
-    fy = (double)sy + (double)cy;
-    fz = (double)sz + (double)cz;
+    lane_sum2<LPA>(mf.sx, mf.cx);
+    lane_sum2<LPA>(mf.sy, mf.cy);
+    lane_sum2<LPA>(mf.sz, mf.cz);
+    fx = (double)mf.sx + (double)mf.cx;
+    fy = (double)mf.sy + (double)mf.cy;
+    fz = (double)mf.sz + (double)mf.cz;
   }
+}
+
+template <int PREC, int LPA>
+__device__ __forceinline__ void pair_forces(const Geometry& g, const State& s, const Tables& t,
+                                            const RepDev& rp, const double4* __restrict__ pos,
+                                            const void* lds_tab, int64_t i, bool active, int sub,
+                                            double4 pi, double& fx, double& fy, double& fz) {
+  const int m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  MixedForce mf;
+  // mixed form: the atom's own record (fixed-point position, F' in float32)
+  const uint4 qi = PREC == 0 ? make_uint4(0u, 0u, 0u, 0u) : s.rec[i];
+  forces_from<PREC, LPA>(g, s, t, rp, pos, lds_tab, i, sub, m, pi, qi, ax, ay, az, mf);
+  forces_end<PREC, LPA>(ax, ay, az, mf, fx, fy, fz);
 }
 
 template <int PREC>
@@ -850,12 +918,10 @@ __device__ __forceinline__ void fill_force_table(void* lds, const Tables& t) {
   }
 }
 
-// Leap-frog update of atom i from its force (Eq. leapfrog): v <- v + dt F
-// ftm2v/m, x' <- x + dt v into pos_out; returns whether it moved more than
-// skin/2 since the last list build (also true for NaN).
-__device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, const RepDev& rp,
-                                         int64_t i, double4 pi, double4 v, double4 xr, double fx,
-                                         double fy, double fz, double4* __restrict__ pos_out) {
+// Leap-frog kick and drift (Eq. leapfrog): v <- v + dt F ftm2v/m, returns
+// x' = x + dt v (w = 0).
+__device__ __forceinline__ double4 kick_drift(const Geometry& g, double4 pi, double4& v, double fx,
+                                              double fy, double fz) {
   const double k = g.dt * g.acc;
   v.x = fma(k, fx, v.x);
   v.y = fma(k, fy, v.y);
@@ -865,15 +931,31 @@ __device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, cons
   xn.y = fma(g.dt, v.y, pi.y);
   xn.z = fma(g.dt, v.z, pi.z);
   xn.w = 0.0;
+  return xn;
+}
+
+// Whether x' moved more than skin/2 from the last list build (also true for
+// NaN); raises ST_NONFINITE on a non-finite force or position.
+__device__ __forceinline__ bool moved_far(const Geometry& g, const State& s, double4 xn, double4 xr,
+                                          double fx, double fy, double fz) {
+  const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
+  const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
+  if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z)) set_bits(s.status, ST_NONFINITE);
+  return !(d2 <= g.lim2);
+}
+
+// Leap-frog update of atom i from its force into pos_out and vel; returns
+// whether it moved more than skin/2 since the last list build.
+__device__ __forceinline__ bool leapfrog(const Geometry& g, const State& s, const RepDev& rp,
+                                         int64_t i, double4 pi, double4 v, double4 xr, double fx,
+                                         double fy, double fz, double4* __restrict__ pos_out) {
+  const double4 xn = kick_drift(g, pi, v, fx, fy, fz);
   pos_out[i] = xn;
   // the mixed form's record goes with the position (pos_out is always the
   // other buffer of s)
   if (s.rec) s.rec_alt[i] = pos_record(rp, xn.x, xn.y, xn.z);
   s.vel[i] = v;
-  const double ex = xn.x - xr.x, ey = xn.y - xr.y, ez = xn.z - xr.z;
-  const double d2 = fma(ex, ex, fma(ey, ey, ez * ez));
-  if (!isfinite(fx + fy + fz) || !isfinite(xn.x + xn.y + xn.z)) set_bits(s.status, ST_NONFINITE);
-  return !(d2 <= g.lim2);
+  return moved_far(g, s, xn, xr, fx, fy, fz);
 }
 
 // Force pass fused with the leap-frog update (Eq. leapfrog):
@@ -1077,6 +1159,12 @@ __global__ __launch_bounds__(PREC == 0 ? 768 : 1024) void k_force_dyn(
 // the phase's global writes of every XCD visible after the barrier.
 constexpr long long kBarrierSpins = 4000000;
 
+// LDS of the density table (rows plus the fill's junk rows), 16-byte aligned.
+__host__ __device__ inline size_t density_table_bytes(int nr, int prec) {
+  const size_t b = (size_t)(nr - 1) * (prec == 0 ? sizeof(double4) : sizeof(float4)) + kLdsJunkBytes;
+  return (b + 15) & ~size_t(15);
+}
+
 // LDS of the force table (rows plus the fill's junk rows), 16-byte aligned.
 __host__ __device__ inline size_t persist_table_bytes(int nr, int prec) {
   const size_t b = (size_t)(nr - 1) * (prec == 0 ? 3 * sizeof(double2)
@@ -1085,27 +1173,45 @@ __host__ __device__ inline size_t persist_table_bytes(int nr, int prec) {
   return (b + 15) & ~size_t(15);
 }
 
-__device__ bool grid_sync(int32_t* status) {
+// Barrier of the np workgroups of a persistent launch (an arrival counter, a
+// generation word and the last arrival's stop decision, all accessed only by
+// atomics; the wait is bounded).  Each thread's stores have completed before
+// its workgroup arrives, and the spin polls with relaxed loads: one fence on
+// each side per workgroup, not one per poll.
+//   kOneL2 = false: the workgroups may sit on different XCDs, whose L2 caches
+//     are not coherent with each other, so the arrival writes this XCD's L2
+//     back and the departure invalidates it (agent-scope release / acquire).
+//   kOneL2 = true: every workgroup runs on the same XCD and so shares one L2:
+//     stores complete into that L2 before the arrival and nothing is written
+//     back, so the lines the phases write stay dirty in the L2, which the
+//     departure's invalidation keeps.  Data that the phases exchange through
+//     atomics (the bin counts) cross full barriers.
+template <bool kOneL2>
+__device__ bool part_sync(int32_t* status, int32_t np) {
   __shared__ int32_t s_go;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (!kOneL2) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     int32_t* count = status + SW_BAR_COUNT;
     int32_t* gen = status + SW_BAR_GEN;
     int32_t* stop = status + SW_BAR_STOP;
-    const int32_t g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);  // the generation is read before the arrival counts
     const int32_t arrived =
-        __hip_atomic_fetch_add(count, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int32_t go = 1;
-    if (arrived == (int32_t)gridDim.x - 1) {
-      const int32_t bits = __hip_atomic_load(status + SW_BITS, __ATOMIC_ACQUIRE,
+    if (arrived == np - 1) {
+      const int32_t bits = __hip_atomic_load(status + SW_BITS, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
       go = (bits & ST_ERR_MASK) ? 0 : 1;
       __hip_atomic_store(count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(stop, go ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(gen, g0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);  // counter and decision are in place before the release
+      __hip_atomic_store(gen, g0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       long long spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
         if (++spins > kBarrierSpins) {
           set_bits(status, ST_STALL);
           go = -1;
@@ -1115,10 +1221,33 @@ __device__ bool grid_sync(int32_t* status) {
       }
       if (go > 0) go = __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 0 : 1;
     }
+    // invalidates this CU's L1 and the clean lines of the L2 (an invalidation
+    // at workgroup scope leaves the L1 alone in a dispatch whose workgroups
+    // are not split over CUs; dirty L2 lines stay, so with one L2 the data of
+    // the phase just ended is still there)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);  // the invalidation is done before any wave reads on
     s_go = go > 0;
   }
   __syncthreads();
   return s_go != 0;
+}
+
+__device__ __forceinline__ bool grid_sync(int32_t* status) {
+  return part_sync<false>(status, (int32_t)gridDim.x);
+}
+
+// The XCD this wave runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcd_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;
+}
+
+// Table position of the it-th atom tile that participant pid of np takes
+// (positions pid, pid + np, ...), or -1 when it has none left.
+__device__ __forceinline__ int64_t walk_tile_of(int64_t it, int64_t n_tiles, int32_t pid,
+                                                int32_t np) {
+  const int64_t b = pid + (int64_t)np * it;
+  return b < n_tiles ? b : -1;
 }
 
 // nsteps whole steps in one cooperative launch (small systems, where graph
@@ -1146,8 +1275,11 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
   int32_t* status = s0.status;
   // the first barrier also publishes one decision on errors latched before the launch
   if (!grid_sync(status)) return;
-  const int64_t gstride = (int64_t)gridDim.x * nwaves;
-  const int64_t gwave = (int64_t)blockIdx.x * nwaves + wave;
+  const int32_t pid = (int32_t)blockIdx.x, np = (int32_t)gridDim.x;
+  auto sync = [&](bool) { return grid_sync(status); };
+  const int64_t gstride = (int64_t)np * nwaves;
+  const int64_t gwave = (int64_t)pid * nwaves + wave;
+  const int tpi = (int)blockDim.x / (64 * LPA);
   for (int32_t step = 0; step < nsteps; ++step) {
     const int k = step & 1;
     const State& s = k ? s1 : s0;
@@ -1155,35 +1287,36 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
     int32_t* fl_nxt = status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
     const int32_t* rf_cur = s.rflag + (k == 0 ? 0 : g.n_rep);
     int32_t* rf_nxt = s.rflag + (k == 0 ? g.n_rep : 0);
+    // written with plain stores before the last barrier: read past the L1
     const bool rebuild =
-        __hip_atomic_load(fl_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        __hip_atomic_load(fl_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
     if (rebuild) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(status, SW_REBUILDS) += 1ull;
+      if (pid == 0 && threadIdx.x == 0) *counter64(status, SW_REBUILDS) += 1ull;
       for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rf_cur, lane);
-      if (!grid_sync(status)) return;
+      if (!sync(true)) return;
       for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
         const CellTile ct = g.ctiles[b];
         if (ct.cell < 0 || rf_cur[ct.rep] == 0) continue;
         build_cell<true>(g, s, ct, L, lane);
         build_sync<true>();  // the wave's next cell reuses its staging arrays
       }
-      if (!grid_sync(status)) return;
+      if (!sync(false)) return;
     }
     // density pass; side jobs: zero the bins after a rebuild, clear the next
     // step's rebuild flags
     if (rebuild) {
-      for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncells;
-           c += (int64_t)gridDim.x * blockDim.x)
+      for (int64_t c = pid * (int64_t)blockDim.x + threadIdx.x; c < ncells;
+           c += (int64_t)np * blockDim.x)
         s.bin_cnt[c] = 0;
     }
-    if (blockIdx.x == 0) {
+    if (pid == 0) {
       if (threadIdx.x == 0) *fl_nxt = 0;
       for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rf_nxt[r] = 0;
     }
     {
       const TileWalk w = tile_walk<LPA>();
-      for (int64_t it = w.q;; it += w.tpi) {
-        const int64_t b = walk_tile(it, g.n_atiles);
+      for (int64_t it = w.q;; it += tpi) {
+        const int64_t b = walk_tile_of(it, g.n_atiles, pid, np);
         if (b < 0) break;
         const AtomTile tl = g.atiles[b];
         const bool active = w.a < tl.count;
@@ -1195,13 +1328,13 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
         store_fprime<PREC>(s, t, s.pos, i, rho_i, 0);
       }
     }
-    if (!grid_sync(status)) return;
+    if (!sync(false)) return;
     // force pass fused with the leap-frog update, into the other buffer
-    if (blockIdx.x == 0 && threadIdx.x == 0) *counter64(status, SW_STEPS) += 1ull;
+    if (pid == 0 && threadIdx.x == 0) *counter64(status, SW_STEPS) += 1ull;
     {
       const TileWalk w = tile_walk<LPA>();
-      for (int64_t it = w.q;; it += w.tpi) {
-        const int64_t b = walk_tile(it, g.n_atiles);
+      for (int64_t it = w.q;; it += tpi) {
+        const int64_t b = walk_tile_of(it, g.n_atiles, pid, np);
         if (b < 0) break;
         const AtomTile tl = g.atiles[b];
         const bool active = w.a < tl.count;
@@ -1223,68 +1356,370 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
         }
       }
     }
-    if (!grid_sync(status)) return;
+    if (!sync(false)) return;
   }
 }
 
-// Binning and list build of a rebuild-check step in one launch, for systems
-// small enough that a grid barrier between the two phases is cheaper than a
-// second graph node (a graph node costs a few microseconds even when it only
-// finds no rebuild due, and in most steps none is).  Phases and barrier are
-// those of k_persist: the same device code, so the list is bitwise that of
-// k_bin + k_build.  The grid never exceeds the workgroups that fit on the chip
-// at once (checked when the context is created), and the barrier's wait is
-// bounded.
-__global__ __launch_bounds__(kPersistThreads) void k_binbuild(Geometry g, State s,
-                                                              const int32_t* cond,
-                                                              const int32_t* rcond) {
-  // the rebuild flag is written only by earlier kernels, so every workgroup
-  // reads the same value: all leave here, or none
-  const int32_t due = cond ? *cond : 1;
-  if (due == 0) return;
-  // the status word is not: an error raised by the binning of one workgroup
-  // may or may not be seen by another at its start.  Every workgroup reaches
-  // the barrier, whose last arrival decides for all whether to go on.
-  const bool err = has_error(s.status);
+// Barrier of the np participants of a persistent launch (np <= kMaxSlots):
+// participant p publishes the barrier's sequence number e in its slot of
+// parity e & 1, and wave 0 of each workgroup polls all np slots at once until
+// every one holds e.  No participant gets more than one barrier ahead of the
+// slowest, so a parity's slots are not rewritten while anyone still reads
+// them.  Each arrival carries whether the participant saw an error latched (its
+// own set_bits completed before it reads the status word), so every
+// participant reads the same slots and takes the same decision.  kWriteBack:
+// the L2 is written back before the arrival (needed when the participants'
+// next phase communicates through atomics, which this barrier does not assume
+// to meet the plain stores in the L2).  The departure invalidates the CU's L1
+// and the clean L2 lines; all participants run on one XCD, whose L2 keeps the
+// dirty lines of the phase just ended.  The slots start at zero (cleared by
+// the host before the launch).
+template <bool kWriteBack>
+__device__ bool slot_sync(int32_t* status, int32_t pid, int32_t np, int32_t& epoch) {
+  __shared__ int32_t s_go;
+  ++epoch;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int32_t* slot = status + SW_SLOTS + kMaxSlots * (epoch & 1);
+    if (threadIdx.x == 0) {
+      if (kWriteBack) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const int32_t bits =
+          __hip_atomic_load(status + SW_BITS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(slot + pid, 2 * epoch + ((bits & ST_ERR_MASK) ? 1 : 0), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int l = (int)threadIdx.x;
+    long long spins = 0;
+    bool stall = false;
+    int32_t v = 2 * epoch;
+    while (true) {
+      v = l < np ? __hip_atomic_load(slot + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                 : 2 * epoch;
+      if (__all((v >> 1) >= epoch)) break;
+      if (++spins > kBarrierSpins) {
+        stall = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    const bool err = __any((v & 1) != 0);
+    if (threadIdx.x == 0) {
+      if (stall) set_bits(status, ST_STALL);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);
+      s_go = !(stall || err);
+    }
+  }
+  __syncthreads();
+  return s_go != 0;
+}
+
+// List entries per lane that the small-system step kernel keeps in registers.
+constexpr int kRegEntries = 8;
+
+// Whole steps of a small system in one launch on one XCD, every thread owning
+// one (atom, lane) slot for the whole launch (the host checks that the atom
+// tiles fit the participants at once).  Each lane keeps its atom's position
+// and F', velocity, list length and first kRegEntries list entries in
+// registers across steps (reloaded after a rebuild), so a pass is the
+// neighbour gathers, the table rows and one store; the density and force
+// passes share the entries.  Phases, their device code and the order of every
+// sum are those of k_persist and of the per-phase kernels: results are bitwise
+// those of the graph path.  Every lane of an atom computes the same update
+// (the lane sums are symmetric), and lane 0 of the atom stores it.
+template <int PREC, int LPA>
+__global__ __launch_bounds__(kPersistThreads) void k_persist_small(Geometry g, State s0,
+                                                                   State s1, Tables t,
+                                                                   int32_t nsteps,
+                                                                   int64_t ncells) {
   extern __shared__ double4 lds_d4[];
+  __shared__ int32_t s_ticket;
+  fill_force_table<PREC>(lds_d4, t);
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int nwaves = (int)blockDim.x >> 6;
   const size_t bl = (build_lds_bytes(g.cell_cap) + 15) & ~size_t(15);
-  const BuildLds L = carve_build_lds(reinterpret_cast<char*>(lds_d4) + (size_t)wave * bl,
-                                     g.cell_cap);
-  if (cond && !err && blockIdx.x == 0 && threadIdx.x == 0) *counter64(s.status, SW_REBUILDS) += 1ull;
-  const int64_t gstride = (int64_t)gridDim.x * nwaves;
-  const int64_t gwave = (int64_t)blockIdx.x * nwaves + wave;
-  if (!err)
-    for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rcond, lane);
-  if (!grid_sync(s.status)) return;
-  for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
-    const CellTile ct = g.ctiles[b];
-    if (ct.cell < 0 || (rcond && rcond[ct.rep] == 0)) continue;
-    build_cell<true>(g, s, ct, L, lane);
-    build_sync<true>();  // the wave's next cell reuses its staging arrays
+  char* build_base = reinterpret_cast<char*>(lds_d4) + persist_table_bytes(t.nr, PREC);
+  const BuildLds L = carve_build_lds(build_base + (size_t)wave * bl, g.cell_cap);
+  const void* dens_tab = PREC == 0 ? static_cast<const void*>(t.rho_val)
+                                   : static_cast<const void*>(t.rho_val32);
+  int32_t* status = s0.status;
+  if (threadIdx.x == 0)
+    s_ticket = xcd_id() == 0
+                   ? __hip_atomic_fetch_add(status + SW_XCD_TICKET, 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                   : -1;
+  // every workgroup meets once (full fences), then those not on XCD 0 leave
+  if (!grid_sync(status)) return;
+  if (s_ticket < 0) return;
+  const int32_t pid = s_ticket;
+  const int32_t np =
+      __hip_atomic_load(status + SW_XCD_TICKET, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int32_t epoch = 0;
+  // every atom tile needs a thread of XCD 0 (the host sized the grid for the
+  // round-robin placement of workgroups over the XCDs); the test is uniform
+  const int tpi = (int)blockDim.x / (64 * LPA);
+  if (np > kMaxSlots || g.n_atiles > (int64_t)np * tpi) {
+    if (pid == 0 && threadIdx.x == 0) set_bits(status, ST_PLACEMENT);
+    return;
+  }
+  const int64_t gstride = (int64_t)np * nwaves;
+  const int64_t gwave = (int64_t)pid * nwaves + wave;
+  // this thread's atom slot
+  const TileWalk w = tile_walk<LPA>();
+  const int64_t tb = walk_tile_of(w.q, g.n_atiles, pid, np);
+  const bool has = tb >= 0;
+  const AtomTile tl = g.atiles[has ? tb : 0];
+  const bool active = has && w.a < tl.count;
+  const RepDev& rp = g.reps[tl.rep];
+  const int64_t i = tl.begin + (active ? w.a : 0);
+  const uint32_t N = (uint32_t)g.n;
+  const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
+  // registers carried across steps
+  int m = 0;
+  uint32_t e[kRegEntries];
+  double4 pi, v = make_double4(0.0, 0.0, 0.0, 0.0), xr = v;
+  uint4 qi = make_uint4(0u, 0u, 0u, 0u);
+  auto load_own = [&](const State& s) {
+    pi = s.pos[i];
+    if (PREC != 0) qi = s.rec[i];
+  };
+  auto load_list = [&](const State& s) {
+    m = active ? min(s.cnt[i], g.nbr_cap) : 0;
+    load_entries<LPA>(s.nbr, N, (uint32_t)i, w.sub, m, self_e, e);
+    xr = s.xref[i];
+  };
+  load_own(s0);
+  load_list(s0);
+  v = s0.vel[i];
+  for (int32_t step = 0; step < nsteps; ++step) {
+    const int k = step & 1;
+    const State& s = k ? s1 : s0;
+    int32_t* fl_cur = status + (k == 0 ? SW_FLAG0 : SW_FLAG1);
+    int32_t* fl_nxt = status + (k == 0 ? SW_FLAG1 : SW_FLAG0);
+    const int32_t* rf_cur = s.rflag + (k == 0 ? 0 : g.n_rep);
+    int32_t* rf_nxt = s.rflag + (k == 0 ? g.n_rep : 0);
+    const bool rebuild =
+        __hip_atomic_load(fl_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+    if (rebuild) {
+      // the bins' zeroing reaches memory before the binning's atomics, and
+      // their counts before the build reads them
+      if (!slot_sync<true>(status, pid, np, epoch)) return;
+      if (pid == 0 && threadIdx.x == 0) *counter64(status, SW_REBUILDS) += 1ull;
+      for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rf_cur, lane);
+      if (!slot_sync<true>(status, pid, np, epoch)) return;
+      for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
+        const CellTile ct = g.ctiles[b];
+        if (ct.cell < 0 || rf_cur[ct.rep] == 0) continue;
+        build_cell<true>(g, s, ct, L, lane);
+        build_sync<true>();  // the wave's next cell reuses its staging arrays
+      }
+      if (!slot_sync<false>(status, pid, np, epoch)) return;
+      // the binning wrapped the positions; the build moved the reference ones
+      load_own(s);
+      load_list(s);
+    }
+    // density pass; side jobs: zero the bins after a rebuild, clear the next
+    // step's rebuild flags
+    if (rebuild) {
+      for (int64_t c = pid * (int64_t)blockDim.x + threadIdx.x; c < ncells;
+           c += (int64_t)np * blockDim.x)
+        s.bin_cnt[c] = 0;
+    }
+    if (pid == 0) {
+      if (threadIdx.x == 0) *fl_nxt = 0;
+      for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rf_nxt[r] = 0;
+    }
+    if (has) {
+      double acc = 0.0;
+      float sum = 0.0f, comp = 0.0f;
+      {
+        double2 qxy[kRegEntries];
+        double qz[kRegEntries];
+        uint4 qr[kRegEntries];
+        const double2* pos2 = reinterpret_cast<const double2*>(s.pos);
+        const double* posd = reinterpret_cast<const double*>(s.pos);
+#pragma unroll
+        for (int u = 0; u < kRegEntries; ++u) {
+          if (PREC == 0) {
+            const uint32_t off = (e[u] & kIndexMask) * 32u;
+            qxy[u] = ld32(pos2, off);
+            qz[u] = ld32(posd, off + 16u);
+          } else {
+            qr[u] = ld32(s.rec, (e[u] & kIndexMask) * 16u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kRegEntries; ++u) {
+          const bool ok = w.sub + u * LPA < m;
+          if (PREC == 0)
+            dens_term64(g, t, rp, dens_tab, e[u], ok, qxy[u], qz[u],
+                        make_double2(pi.x, pi.y), pi.z, acc);
+          else dens_term32(g, t, rp, dens_tab, ok, qr[u], qi, sum, comp);
+        }
+      }
+      if (w.sub + kRegEntries * LPA < m)
+        density_from<PREC, LPA>(g, s, t, rp, s.pos, dens_tab, i, w.sub + kRegEntries * LPA, m,
+                                make_double2(pi.x, pi.y), pi.z, qi, acc, sum, comp);
+      const double rho_i = density_end<PREC, LPA>(acc, sum, comp);
+      bool beyond = false;
+      const double fp = fprime_of<PREC>(t, rho_i, beyond);
+      pi.w = fp;
+      if (PREC != 0) qi.w = __float_as_uint((float)fp);
+      if (active && w.sub == 0) {
+        if (PREC != 0) s.rec[i].w = qi.w;
+        s.pos[i].w = fp;
+        if (beyond) set_bits(s.status, ST_RHO_RANGE);
+      }
+    }
+    if (!slot_sync<false>(status, pid, np, epoch)) return;
+    // force pass fused with the leap-frog update, into the other buffer
+    if (pid == 0 && threadIdx.x == 0) *counter64(status, SW_STEPS) += 1ull;
+    if (has) {
+      double ax = 0.0, ay = 0.0, az = 0.0;
+      MixedForce mf;
+      {
+        double4 q[kRegEntries];
+        uint4 qr[kRegEntries];
+#pragma unroll
+        for (int u = 0; u < kRegEntries; ++u) {
+          if (PREC == 0) q[u] = ld32(s.pos, (e[u] & kIndexMask) * 32u);
+          else qr[u] = ld32(s.rec, (e[u] & kIndexMask) * 16u);
+        }
+        const float fpi = PREC == 0 ? 0.0f : __uint_as_float(qi.w);
+#pragma unroll
+        for (int u = 0; u < kRegEntries; ++u) {
+          const bool ok = w.sub + u * LPA < m;
+          if (PREC == 0) force_term64(g, t, rp, lds_d4, e[u], ok, q[u], pi, ax, ay, az);
+          else force_term32(g, t, rp, lds_d4, ok, qr[u], qi, fpi, mf);
+        }
+      }
+      if (w.sub + kRegEntries * LPA < m)
+        forces_from<PREC, LPA>(g, s, t, rp, s.pos, lds_d4, i, w.sub + kRegEntries * LPA, m, pi,
+                               qi, ax, ay, az, mf);
+      double fx, fy, fz;
+      forces_end<PREC, LPA>(ax, ay, az, mf, fx, fy, fz);
+      bool far = false;
+      if (active) {
+        const double4 xn = kick_drift(g, pi, v, fx, fy, fz);
+        if (w.sub == 0) {
+          s.pos_alt[i] = xn;
+          if (PREC != 0) s.rec_alt[i] = pos_record(rp, xn.x, xn.y, xn.z);
+          s.vel[i] = v;
+          far = moved_far(g, s, xn, xr, fx, fy, fz);
+        }
+        pi = xn;
+        if (PREC != 0) qi = pos_record(rp, xn.x, xn.y, xn.z);
+      }
+      if (__ballot(far) != 0ull && lane_id() == 0) {
+        *fl_nxt = 1;
+        rf_nxt[tl.rep] = 1;
+      }
+    }
+    if (!slot_sync<false>(status, pid, np, epoch)) return;
   }
 }
 
-size_t binbuild_lds_bytes(int cell_cap) {
-  return (size_t)(kPersistThreads / 64) * ((build_lds_bytes(cell_cap) + 15) & ~size_t(15));
+// Binning, list build and density pass of a step in one launch, for systems
+// small enough that grid barriers between the phases are cheaper than graph
+// nodes (a node costs a few microseconds even when it only finds no rebuild
+// due, and in most steps none is).  When the step's rebuild flag is set:
+// binning, barrier, list build, barrier (then the bins are cleared); in every
+// step: the density pass and F'.  The phases are the device code of k_bin,
+// k_build and k_density (results are bitwise theirs) and the barrier is the
+// persistent kernel's bounded one.  The density rows sit in the LDS beside
+// the build's per-wave staging.  The grid never exceeds the workgroups that fit
+// on the chip at once (checked when the context is created).  Side jobs as in
+// k_density: clear the next step's rebuild flags.
+template <int PREC, int LPA>
+__global__ __launch_bounds__(kPersistThreads) void k_bin_build_density(
+    Geometry g, State s, Tables t, const int32_t* cond, const int32_t* rcond,
+    int32_t* clear_flag, int32_t* rclear, int64_t ncells) {
+  extern __shared__ double4 lds_d4[];
+  // the rebuild flag is written only by earlier kernels, so every workgroup
+  // reads the same value; the status word is not (an error raised by the
+  // binning of one workgroup may or may not be seen by another at its start),
+  // so the barriers' last arrivals decide for all whether to go on
+  const int32_t due = cond ? *cond : 1;
+  const bool err = has_error(s.status);
+  if (clear_flag && blockIdx.x == 0) {
+    if (threadIdx.x == 0) *clear_flag = 0;
+    for (int r = threadIdx.x; r < g.n_rep; r += blockDim.x) rclear[r] = 0;
+  }
+  if (PREC == 0) lds_fill<4>(lds_d4, t.rho_val, t.nr - 1, lds_d4 + (t.nr - 1));
+  else
+    lds_fill<4>(reinterpret_cast<float4*>(lds_d4), t.rho_val32, t.nr - 1,
+                reinterpret_cast<float4*>(lds_d4) + (t.nr - 1));
+  if (due) {
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int nwaves = (int)blockDim.x >> 6;
+    const size_t bl = (build_lds_bytes(g.cell_cap) + 15) & ~size_t(15);
+    char* base = reinterpret_cast<char*>(lds_d4) + density_table_bytes(t.nr, PREC);
+    const BuildLds L = carve_build_lds(base + (size_t)wave * bl, g.cell_cap);
+    if (cond && !err && blockIdx.x == 0 && threadIdx.x == 0)
+      *counter64(s.status, SW_REBUILDS) += 1ull;
+    const int64_t gstride = (int64_t)gridDim.x * nwaves;
+    const int64_t gwave = (int64_t)blockIdx.x * nwaves + wave;
+    if (!err)
+      for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rcond, lane);
+    if (!grid_sync(s.status)) return;
+    for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
+      const CellTile ct = g.ctiles[b];
+      if (ct.cell < 0 || (rcond && rcond[ct.rep] == 0)) continue;
+      build_cell<true>(g, s, ct, L, lane);
+      build_sync<true>();  // the wave's next cell reuses its staging arrays
+    }
+    if (!grid_sync(s.status)) return;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncells;
+         c += (int64_t)gridDim.x * blockDim.x)
+      s.bin_cnt[c] = 0;
+  } else {
+    __syncthreads();  // the table is in place
+    if (err) return;
+  }
+  const TileWalk w = tile_walk<LPA>();
+  for (int64_t it = w.q;; it += w.tpi) {
+    const int64_t b = walk_tile(it, g.n_atiles);
+    if (b < 0) break;
+    const AtomTile tl = g.atiles[b];
+    const bool active = w.a < tl.count;
+    const RepDev& rp = g.reps[tl.rep];
+    const int64_t i = tl.begin + (active ? w.a : 0);
+    const double rho_i = density_of<PREC, LPA>(g, s, t, rp, s.pos, lds_d4, i, active, w.sub);
+    if (!active || w.sub != 0) continue;
+    store_fprime<PREC>(s, t, s.pos, i, rho_i, 0);
+  }
 }
 
-int binbuild_blocks_per_cu(int cell_cap) {
+size_t bbd_lds_bytes(const Tables& t, int prec, int cell_cap) {
+  return density_table_bytes(t.nr, prec) +
+         (size_t)(kPersistThreads / 64) * ((build_lds_bytes(cell_cap) + 15) & ~size_t(15));
+}
+
+template <int PREC, int LPA>
+static int bbd_fit_one(size_t bytes) {
+  const void* fn = reinterpret_cast<const void*>(&k_bin_build_density<PREC, LPA>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+      hipSuccess)
+    return 0;
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_binbuild),
-                                                   kPersistThreads,
-                                                   binbuild_lds_bytes(cell_cap)) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPersistThreads, bytes) != hipSuccess)
     return 0;
   return n;
 }
 
-hipError_t launch_binbuild(const Launch& L, const Geometry& g, const State& s,
-                           const int32_t* cond, const int32_t* rcond, int grid) {
-  hipLaunchKernelGGL(k_binbuild, dim3(grid), dim3(kPersistThreads),
-                     binbuild_lds_bytes(g.cell_cap), L.stream, g, s, cond, rcond);
-  return hipGetLastError();
+int bbd_blocks_per_cu(const Tables& t, int precision, int cell_cap) {
+  const size_t b = bbd_lds_bytes(t, precision, cell_cap);
+  int n;
+  if (precision == 0)
+    n = std::min(std::min(bbd_fit_one<0, 1>(b), bbd_fit_one<0, 2>(b)),
+                 std::min(bbd_fit_one<0, 4>(b), bbd_fit_one<0, 8>(b)));
+  else
+    n = std::min(std::min(bbd_fit_one<1, 1>(b), bbd_fit_one<1, 2>(b)),
+                 std::min(bbd_fit_one<1, 4>(b), bbd_fit_one<1, 8>(b)));
+  return n;
 }
+
 
 __global__ __launch_bounds__(64) void k_halfkick(Geometry g, State s, double coef) {
   const AtomTile tl = g.atiles[blockIdx.x];
@@ -1561,6 +1996,27 @@ hipError_t launch_force_only(const Launch& L, const Geometry& g, const State& s,
 #undef MDK_O
 }
 
+template <int PREC, int LPA>
+static hipError_t bbd_go(const Launch& L, const Geometry& g, const State& s, const Tables& t,
+                         const int32_t* cond, const int32_t* rcond, int32_t* clear_flag,
+                         int32_t* rclear, int64_t ncells, int grid) {
+  hipLaunchKernelGGL((k_bin_build_density<PREC, LPA>), dim3(grid), dim3(kPersistThreads),
+                     bbd_lds_bytes(t, PREC, g.cell_cap), L.stream, g, s, t, cond, rcond,
+                     clear_flag, rclear, ncells);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_build_density(const Launch& L, const Geometry& g, const State& s,
+                                    const Tables& t, int precision, int lpa,
+                                    const int32_t* cond, const int32_t* rcond,
+                                    int32_t* clear_flag, int32_t* rclear, int64_t ncells,
+                                    int grid) {
+#define MDK_B(P, Lp) bbd_go<P, Lp>(L, g, s, t, cond, rcond, clear_flag, rclear, ncells, grid)
+  if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_B) }
+  MDK_LPA_SWITCH(1, lpa, MDK_B)
+#undef MDK_B
+}
+
 hipError_t launch_density_dyn(const Launch& L, const Geometry& g, const State& s, const Tables& t,
                               int precision, const double4* pos, const int32_t* cond_zero,
                               int32_t* clear_flag, int32_t* rclear, int64_t n_cells_total,
@@ -1604,22 +2060,25 @@ size_t persist_lds_bytes(const Tables& t, int prec, int cell_cap) {
 
 template <int PREC, int LPA>
 static hipError_t persist_go(const Launch& L, const Geometry& g, const State& s0, const State& s1,
-                             const Tables& t, int32_t nsteps, int64_t ncells, int grid) {
+                             const Tables& t, int32_t nsteps, int64_t ncells, int grid,
+                             int small) {
   Geometry ga = g;
   State a0 = s0, a1 = s1;
   Tables ta = t;
   int32_t n = nsteps;
   int64_t m = ncells;
   void* args[] = {&ga, &a0, &a1, &ta, &n, &m};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<PREC, LPA>),
+  const void* fn = small ? reinterpret_cast<const void*>(&k_persist_small<PREC, LPA>)
+                         : reinterpret_cast<const void*>(&k_persist<PREC, LPA>);
+  return hipLaunchCooperativeKernel(fn,
                                     dim3(grid), dim3(kPersistThreads), args,
                                     (unsigned int)persist_lds_bytes(t, PREC, g.cell_cap), L.stream);
 }
 
 hipError_t launch_persist(const Launch& L, const Geometry& g, const State& s0, const State& s1,
                           const Tables& t, int precision, int lpa, int32_t nsteps, int64_t ncells,
-                          int grid) {
-#define MDK_P(P, Lp) persist_go<P, Lp>(L, g, s0, s1, t, nsteps, ncells, grid)
+                          int grid, int small) {
+#define MDK_P(P, Lp) persist_go<P, Lp>(L, g, s0, s1, t, nsteps, ncells, grid, small)
   if (precision == 0) { MDK_LPA_SWITCH(0, lpa, MDK_P) }
   MDK_LPA_SWITCH(1, lpa, MDK_P)
 #undef MDK_P
@@ -1627,7 +2086,10 @@ hipError_t launch_persist(const Launch& L, const Geometry& g, const State& s0, c
 
 template <int PREC, int LPA>
 static hipError_t allow_persist_one(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist<PREC, LPA>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist<PREC, LPA>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist_small<PREC, LPA>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

@@ -1,6 +1,12 @@
 """The persistent launch (one cooperative kernel per chunk, grid barriers
 between phases) runs the same device code as the graph path: trajectories,
-forces, counters and error handling must be bitwise those of the graph."""
+forces, counters and error handling must be bitwise those of the graph.
+
+Systems whose atom tiles fit one thread slot each on the workgroups of one XCD
+run the small-system kernel (state in registers, slot barriers on one L2);
+the cases named all_xcds_* are too large for it (8,192 atoms at 8 lanes per
+atom: 128 tiles for at most 32 workgroups) and run the kernel that spreads
+its workgroups over every XCD."""
 import sys
 
 import numpy as np
@@ -63,6 +69,10 @@ CASES = [
     ("slab_open", lambda: [configs.slab(8, 8, 5, seed=31)], 60, dict(chunk_steps=20)),
     ("resort_every_chunk", lambda: [configs.small_box(8, seed=45, temperature=2500.0)], 80,
      dict(chunk_steps=20, sort_every=1)),
+    ("all_xcds_8192", lambda: [configs.small_box(16, seed=47, temperature=2500.0)], 60,
+     dict(chunk_steps=20, lanes_per_atom=8)),
+    ("all_xcds_mixed", lambda: [configs.small_box(16, seed=48, temperature=2500.0)], 40,
+     dict(chunk_steps=20, lanes_per_atom=8, precision=1)),
 ]
 
 
@@ -92,15 +102,17 @@ def test_persistent_matches_oracle(md, tabs, oracle_lib):
     assert np.max(np.abs(v - out["v"])) < 1e-11
 
 
-def test_persistent_overflow_rolls_back_like_the_graph(md, tabs):
+# list capacities just above each box's initial longest list (29 and 31 entries)
+@pytest.mark.parametrize("cells,lpa,cap", [(8, 0, 30), (16, 8, 32)], ids=["small_kernel", "all_xcds"])
+def test_persistent_overflow_rolls_back_like_the_graph(md, tabs, cells, lpa, cap):
     """A list overflow in a rebuild inside the chunk stops every workgroup at
     the same barrier; the chunk rolls back to its snapshot, as in the graph."""
-    box = configs.small_box(8, seed=46, temperature=2500.0, sigma_x=0.05)
-    _say(f"[gpu] persistent overflow n={box.n}")
+    box = configs.small_box(cells, seed=46, temperature=2500.0, sigma_x=0.05)
+    _say(f"[gpu] persistent overflow n={box.n} lpa={lpa}")
     g = _run(md, tabs, [box], 60, md.MD_LAUNCH_GRAPH, check=False, chunk_steps=20,
-             nbr_capacity=30)
+             nbr_capacity=cap, lanes_per_atom=lpa)
     p = _run(md, tabs, [box], 60, md.MD_LAUNCH_PERSISTENT, check=False, chunk_steps=20,
-             nbr_capacity=30)
+             nbr_capacity=cap, lanes_per_atom=lpa)
     assert g[0] == md.MD_E_NBR_OVERFLOW and p[0] == md.MD_E_NBR_OVERFLOW
     for a, b in zip(g[1:3], p[1:3]):
         assert np.array_equal(a, b)
