@@ -283,10 +283,12 @@ def bench_headline(torch, md, configs, tabs, args, copy_gbs):
 
 # ------------------------------------------------------------------ secondaries
 
-def bench_c1(torch, md, configs, tabs):
+def bench_c1(torch, md, configs, tabs, persistent=True):
     """2,000-atom box (launch-latency regime): 100 steps as one captured graph
     from the prepared state (the workload's own length), a longer 2,000-step
-    window, and one persistent cooperative launch per chunk for comparison."""
+    window, and one persistent cooperative launch per chunk for comparison
+    (skipped with persistent=False: rocprofv3 ends with a segmentation fault
+    after cooperative launches, before it writes its results)."""
     box = configs.config_small()
     s = make_system(md, box, tabs, precision=md.MD_FP64)
     lpa, _ = s.autotune(50)
@@ -298,11 +300,13 @@ def bench_c1(torch, md, configs, tabs):
     sec, _ = time_steps(torch, s, 2000)
     st = s.stats()
     s.close()
-    sp = make_system(md, box, tabs, precision=md.MD_FP64, lpa=8,
-                     launch_mode=md.MD_LAUNCH_PERSISTENT)
-    sp.step(100)
-    sec_p, _ = time_steps(torch, sp, 2000)
-    sp.close()
+    sec_p = None
+    if persistent:
+        sp = make_system(md, box, tabs, precision=md.MD_FP64, lpa=8,
+                         launch_mode=md.MD_LAUNCH_PERSISTENT)
+        sp.step(100)
+        sec_p, _ = time_steps(torch, sp, 2000)
+        sp.close()
     return {"n_atoms": box.n, "lanes_per_atom": lpa,
             "steps_100": {"timesteps_per_s": round(100 / sec100, 1),
                           "atom_steps_per_s": round(100 / sec100 * box.n, 1),
@@ -312,7 +316,7 @@ def bench_c1(torch, md, configs, tabs):
                            "atom_steps_per_s": round(2000 / sec * box.n, 1),
                            "us_per_step": round(sec / 2000 * 1e6, 3)},
             "rebuilds": st["rebuilds"],
-            "persistent_launch_timesteps_per_s": round(2000 / sec_p, 1)}
+            "persistent_launch_timesteps_per_s": round(2000 / sec_p, 1) if sec_p else None}
 
 
 def bench_c2_series(torch, md, configs, tabs, steps=10000):
@@ -860,6 +864,8 @@ def main() -> int:
     ap.add_argument("--secondary-steps", type=int, default=5000)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--lpa", type=int, default=0)
+    ap.add_argument("--c1-graph-only", action="store_true",
+                    help="c1 without its persistent-launch comparison (for rocprofv3 runs)")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--sequential-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=512,
@@ -897,7 +903,7 @@ def main() -> int:
     sections = set() if args.no_secondary else set(args.sections.split(","))
     big, snaps, fm_problem = None, [], None
     if "c1" in sections:
-        out["c1_2000"] = bench_c1(torch, md, configs, tabs)
+        out["c1_2000"] = bench_c1(torch, md, configs, tabs, persistent=not args.c1_graph_only)
         log(f"  c1: {out['c1_2000']}")
     if "c2" in sections:
         out["c2_10000"] = bench_c2_series(torch, md, configs, tabs)
