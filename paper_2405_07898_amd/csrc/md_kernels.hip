@@ -281,36 +281,31 @@ __device__ __forceinline__ void build_sync() {
   }
 }
 
-template <bool kWave>
-__device__ __forceinline__ void build_cell(const Geometry& g, const State& s, const CellTile& ct,
-                                           const BuildLds& L, int lane) {
-  const RepDev& rp = g.reps[ct.rep];
+// Stencil cell `lane` (< 27) of cell c: its global index, image code and
+// whether it lies past an open dimension's grid edge (then it is empty).
+__device__ __forceinline__ void stencil_cell(const RepDev& rp, int32_t c, int lane, int32_t& q,
+                                             int32_t& code, bool& outside) {
   const int32_t nx = rp.nc[0], ny = rp.nc[1], nz = rp.nc[2];
-  const int32_t c = ct.cell;
   const int32_t cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-  const int32_t ccap = g.cell_cap;
-  // stencil cells: lane k < 27 owns cell k (z-major, then y, then x)
-  int32_t n = 0;
-  if (lane < 27) {
-    const int dz = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dx = lane % 3 - 1;
-    const int32_t ux = cx + dx, uy = cy + dy, uz = cz + dz;
-    // wrapped index below 0: candidate near L, shift -L (code 0); above: +L (code 2)
-    uint32_t kx = ux < 0 ? 0u : (ux >= nx ? 2u : 1u);
-    uint32_t ky = uy < 0 ? 0u : (uy >= ny ? 2u : 1u);
-    uint32_t kz = uz < 0 ? 0u : (uz >= nz ? 2u : 1u);
-    // an open dimension has no image: a stencil cell past its grid edge is empty
-    const bool outside = (((rp.open & 1) && kx != 1u) || ((rp.open & 2) && ky != 1u) ||
-                          ((rp.open & 4) && kz != 1u));
-    if (rp.open & 1) kx = 1u;
-    if (rp.open & 2) ky = 1u;
-    if (rp.open & 4) kz = 1u;
-    const int32_t q = rp.cell0 + (((uz + nz) % nz) * ny + (uy + ny) % ny) * nx + (ux + nx) % nx;
-    n = outside ? 0 : min(s.bin_cnt[q], ccap);
-    L.q[lane] = q;
-    L.n[lane] = n;
-    L.code[lane] = (int32_t)(kx | (ky << 2) | (kz << 4));
-  }
-  // exclusive prefix of the 27 counts across the wave
+  const int dz = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dx = lane % 3 - 1;
+  const int32_t ux = cx + dx, uy = cy + dy, uz = cz + dz;
+  // wrapped index below 0: candidate near L, shift -L (code 0); above: +L (code 2)
+  uint32_t kx = ux < 0 ? 0u : (ux >= nx ? 2u : 1u);
+  uint32_t ky = uy < 0 ? 0u : (uy >= ny ? 2u : 1u);
+  uint32_t kz = uz < 0 ? 0u : (uz >= nz ? 2u : 1u);
+  // an open dimension has no image: a stencil cell past its grid edge is empty
+  outside = (((rp.open & 1) && kx != 1u) || ((rp.open & 2) && ky != 1u) ||
+             ((rp.open & 4) && kz != 1u));
+  if (rp.open & 1) kx = 1u;
+  if (rp.open & 2) ky = 1u;
+  if (rp.open & 4) kz = 1u;
+  q = rp.cell0 + (((uz + nz) % nz) * ny + (uy + ny) % ny) * nx + (ux + nx) % nx;
+  code = (int32_t)(kx | (ky << 2) | (kz << 4));
+}
+
+// Exclusive prefix of the 27 stencil counts (lane k holds n_k) into L.off.
+template <bool kWave>
+__device__ __forceinline__ void stencil_offsets(const BuildLds& L, int lane, int32_t n) {
   int32_t incl = n;
 #pragma unroll
   for (int o = 1; o < 32; o <<= 1) {
@@ -320,6 +315,144 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
   if (lane < 27) L.off[lane] = incl - n;
   if (lane == 26) L.off[27] = incl;
   build_sync<kWave>();
+}
+
+// Staged candidates p < T (ids in L.raw, stencil cell in L.cell) ordered by id
+// within their stencil cell into L.idx.
+template <bool kWave>
+__device__ __forceinline__ void rank_stage(const BuildLds& L, int lane, int T, int base_off) {
+  for (int p = lane; p < T; p += 64) {
+    const int sc = L.cell[p];
+    const int lo = L.off[sc] - base_off, nn = L.n[sc];
+    const int32_t e = L.raw[p];
+    int r = 0;
+    for (int w = lo; w < lo + nn; ++w) r += (L.raw[w] < e);
+    L.idx[lo + r] = e;
+  }
+  build_sync<kWave>();
+}
+
+// The distance tests of every centre atom against the staged candidates
+// (positions px.., image shifts sx.., entries ent.. in registers, T of them),
+// appending the admitted ones to the centre atoms' rows in candidate order.
+__device__ __forceinline__ void test_stage(const Geometry& g, const State& s, const RepDev& rp,
+                                           const BuildLds& L, int lane, int T, int n_c,
+                                           const double (&px)[kBuildChunks],
+                                           const double (&py)[kBuildChunks],
+                                           const double (&pz)[kBuildChunks],
+                                           const double (&sx)[kBuildChunks],
+                                           const double (&sy)[kBuildChunks],
+                                           const double (&sz)[kBuildChunks],
+                                           const uint32_t (&ent)[kBuildChunks]) {
+  const double Lx = rp.box[0], Ly = rp.box[1], Lz = rp.box[2];
+  const double rl2 = g.rl2;
+  const int64_t N = g.n;
+  const int32_t cap = g.nbr_cap;
+  for (int u = 0; u < n_c; ++u) {
+    const int32_t i = L.center[u];
+    const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
+    const double qx = L.cx[u], qy = L.cy[u], qz = L.cz[u];
+    int base = L.base[u];
+#pragma unroll
+    for (int k = 0; k < kBuildChunks; ++k) {
+      if (k * 64 >= T) break;
+      const double dx = fma(sx[k], Lx, px[k] - qx);
+      const double dy = fma(sy[k], Ly, py[k] - qy);
+      const double dz = fma(sz[k], Lz, pz[k] - qz);
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      // the centre atom itself is the only candidate with its own id in the
+      // centre cell (code kNoShift)
+      const bool ok = ent[k] != self_e && r2 < rl2;
+      const unsigned long long m = __ballot(ok);
+      if (ok) {
+        const uint32_t kk = (uint32_t)base + __builtin_amdgcn_mbcnt_hi(
+                                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (kk < (uint32_t)cap) st32(s.nbr, (kk * (uint32_t)N + (uint32_t)i) * 4u, ent[k]);
+      }
+      base += __popcll(m);
+    }
+    if (lane == 0) L.base[u] = base;
+  }
+}
+
+// List lengths of the centre atoms, and the cell's statistics and overflow checks.
+__device__ __forceinline__ void finish_cell(const Geometry& g, const State& s, const BuildLds& L,
+                                            int lane, int n_c, int32_t qc) {
+  int32_t mx = 0;
+  long long tot = 0;
+  for (int u = lane; u < n_c; u += 64) {
+    const int32_t b = L.base[u];
+    s.cnt[L.center[u]] = b;
+    mx = max(mx, b);
+    tot += b;
+  }
+  mx = wave_max_i32(mx);
+  tot = wave_sum_i64(tot);
+  if (lane == 0) {
+    // per-cell statistics (reduced on demand); the status word is only
+    // touched in the rare overflow cases
+    const int32_t full = s.bin_cnt[qc];
+    s.cell_stat[3 * (int64_t)qc + 0] = mx;
+    s.cell_stat[3 * (int64_t)qc + 1] = (int32_t)tot;
+    s.cell_stat[3 * (int64_t)qc + 2] = full;
+    if (mx > g.nbr_cap) set_bits(s.status, ST_NBR_OVERFLOW);
+    if (full > g.cell_cap) set_bits(s.status, ST_CELL_OVERFLOW);
+  }
+}
+
+// Candidate registers of stage slots p = k * 64 + lane (< T): position, image
+// shift and list entry; empty slots sit infinitely far away (r^2 = inf fails).
+__device__ __forceinline__ void load_candidates(const State& s, const BuildLds& L, int lane, int T,
+                                                double (&px)[kBuildChunks],
+                                                double (&py)[kBuildChunks],
+                                                double (&pz)[kBuildChunks],
+                                                double (&sx)[kBuildChunks],
+                                                double (&sy)[kBuildChunks],
+                                                double (&sz)[kBuildChunks],
+                                                uint32_t (&ent)[kBuildChunks]) {
+#pragma unroll
+  for (int k = 0; k < kBuildChunks; ++k) {
+    const int p = k * 64 + lane;
+    px[k] = py[k] = pz[k] = HUGE_VAL;
+    sx[k] = sy[k] = sz[k] = 0.0;
+    ent[k] = 0xffffffffu;
+    if (p < T) {
+      const int32_t j = L.idx[p];
+      const uint32_t code = (uint32_t)L.code[L.cell[p]];
+      const double4 q = s.pos[j];
+      px[k] = q.x;
+      py[k] = q.y;
+      pz[k] = q.z;
+      sx[k] = (double)((int)(code & 3u) - 1);
+      sy[k] = (double)((int)((code >> 2) & 3u) - 1);
+      sz[k] = (double)((int)(code >> 4) - 1);
+      ent[k] = (uint32_t)j | (code << kIndexBits);
+    }
+  }
+}
+
+// The list rows of one cell's atoms: every atom of the 27 stencil cells is a
+// candidate (Sec. III-C: the candidate filter), admitted when r^2 < (r_c +
+// skin)^2 under the stencil cell's image shift; rows in stencil-cell order,
+// by id within a cell.  The stencil's candidates are staged in batches of at
+// most kMaxStage.
+template <bool kWave>
+__device__ __forceinline__ void build_cell(const Geometry& g, const State& s, const CellTile& ct,
+                                           const BuildLds& L, int lane) {
+  const RepDev& rp = g.reps[ct.rep];
+  const int32_t ccap = g.cell_cap;
+  // stencil cells: lane k < 27 owns cell k (z-major, then y, then x)
+  int32_t n = 0;
+  if (lane < 27) {
+    int32_t q, code;
+    bool outside;
+    stencil_cell(rp, ct.cell, lane, q, code, outside);
+    n = outside ? 0 : min(s.bin_cnt[q], ccap);
+    L.q[lane] = q;
+    L.n[lane] = n;
+    L.code[lane] = code;
+  }
+  stencil_offsets<kWave>(L, lane, n);
   // centre atoms in increasing index, with their positions
   const int32_t qc = L.q[13], n_c = L.n[13];
   for (int u = lane; u < n_c; u += 64) L.raw[u] = s.bin_idx[(int64_t)qc * ccap + u];
@@ -336,10 +469,6 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
     L.cz[r] = q.z;
   }
   build_sync<kWave>();
-  const double Lx = rp.box[0], Ly = rp.box[1], Lz = rp.box[2];
-  const double rl2 = g.rl2;
-  const int64_t N = g.n;
-  const int32_t cap = g.nbr_cap;
   int s0 = 0;
   while (s0 < 27) {
     // the largest run of stencil cells whose candidates fit the stage (one
@@ -359,87 +488,17 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
       L.raw[p] = s.bin_idx[(int64_t)L.q[sc] * ccap + (p + base_off - L.off[sc])];
     }
     build_sync<kWave>();
-    for (int p = lane; p < T; p += 64) {
-      const int sc = L.cell[p];
-      const int lo = L.off[sc] - base_off, nn = L.n[sc];
-      const int32_t e = L.raw[p];
-      int r = 0;
-      for (int w = lo; w < lo + nn; ++w) r += (L.raw[w] < e);
-      L.idx[lo + r] = e;
-    }
-    build_sync<kWave>();
+    rank_stage<kWave>(L, lane, T, base_off);
     // candidates into registers (L.cell is per stencil cell, unchanged by the sort)
     double px[kBuildChunks], py[kBuildChunks], pz[kBuildChunks];
     double sx[kBuildChunks], sy[kBuildChunks], sz[kBuildChunks];
     uint32_t ent[kBuildChunks];
-#pragma unroll
-    for (int k = 0; k < kBuildChunks; ++k) {
-      const int p = k * 64 + lane;
-      // empty slots sit infinitely far away: r^2 = inf fails the test
-      px[k] = py[k] = pz[k] = HUGE_VAL;
-      sx[k] = sy[k] = sz[k] = 0.0;
-      ent[k] = 0xffffffffu;
-      if (p < T) {
-        const int32_t j = L.idx[p];
-        const uint32_t code = (uint32_t)L.code[L.cell[p]];
-        const double4 q = s.pos[j];
-        px[k] = q.x;
-        py[k] = q.y;
-        pz[k] = q.z;
-        sx[k] = (double)((int)(code & 3u) - 1);
-        sy[k] = (double)((int)((code >> 2) & 3u) - 1);
-        sz[k] = (double)((int)(code >> 4) - 1);
-        ent[k] = (uint32_t)j | (code << kIndexBits);
-      }
-    }
-    for (int u = 0; u < n_c; ++u) {
-      const int32_t i = L.center[u];
-      const uint32_t self_e = (uint32_t)i | (kNoShift << kIndexBits);
-      const double qx = L.cx[u], qy = L.cy[u], qz = L.cz[u];
-      int base = L.base[u];
-#pragma unroll
-      for (int k = 0; k < kBuildChunks; ++k) {
-        if (k * 64 >= T) break;
-        const double dx = fma(sx[k], Lx, px[k] - qx);
-        const double dy = fma(sy[k], Ly, py[k] - qy);
-        const double dz = fma(sz[k], Lz, pz[k] - qz);
-        const double r2 = (dx * dx + dy * dy) + dz * dz;
-        // the centre atom itself is the only candidate with its own id in the
-        // centre cell (code kNoShift)
-        const bool ok = ent[k] != self_e && r2 < rl2;
-        const unsigned long long m = __ballot(ok);
-        if (ok) {
-          const uint32_t kk = (uint32_t)base + __builtin_amdgcn_mbcnt_hi(
-                                   (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (kk < (uint32_t)cap) st32(s.nbr, (kk * (uint32_t)N + (uint32_t)i) * 4u, ent[k]);
-        }
-        base += __popcll(m);
-      }
-      if (lane == 0) L.base[u] = base;
-    }
+    load_candidates(s, L, lane, T, px, py, pz, sx, sy, sz, ent);
+    test_stage(g, s, rp, L, lane, T, n_c, px, py, pz, sx, sy, sz, ent);
     build_sync<kWave>();
     s0 = s1;
   }
-  int32_t mx = 0;
-  long long tot = 0;
-  for (int u = lane; u < n_c; u += 64) {
-    const int32_t b = L.base[u];
-    s.cnt[L.center[u]] = b;
-    mx = max(mx, b);
-    tot += b;
-  }
-  mx = wave_max_i32(mx);
-  tot = wave_sum_i64(tot);
-  if (lane == 0) {
-    // per-cell statistics (reduced on demand); the status word is only
-    // touched in the rare overflow cases
-    const int32_t full = s.bin_cnt[qc];
-    s.cell_stat[3 * (int64_t)qc + 0] = mx;
-    s.cell_stat[3 * (int64_t)qc + 1] = (int32_t)tot;
-    s.cell_stat[3 * (int64_t)qc + 2] = full;
-    if (mx > cap) set_bits(s.status, ST_NBR_OVERFLOW);
-    if (full > ccap) set_bits(s.status, ST_CELL_OVERFLOW);
-  }
+  finish_cell(g, s, L, lane, n_c, qc);
 }
 
 // Launched with a grid smaller than the cell count (workgroup b takes cell
