@@ -225,6 +225,10 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
 // bit-identical to the reference's; pairs at other images are farther than the
 // list radius under either rule.
 constexpr int kBuildChunks = kMaxStage / 64;
+// Candidates staged per batch in the small-system node, whose 512-thread
+// workgroups have registers to spare: at about 9 atoms per cell a stencil
+// often holds more than kMaxStage, and a second batch doubles the cell's chain.
+constexpr int kSmallStage = 384;
 
 // LDS of one build workgroup; the centre-cell arrays are sized by the cell
 // capacity at launch (dynamic shared memory).
@@ -243,12 +247,12 @@ struct BuildLds {
   int8_t* cell;     // [kMaxStage] stencil cell of each staged slot
 };
 
-__host__ __device__ inline size_t build_lds_bytes(int ccap) {
-  return sizeof(int32_t) * (27 * 3 + 28 + 2 * (size_t)kMaxStage + 2 * (size_t)ccap) +
-         sizeof(double) * 3 * (size_t)ccap + (size_t)kMaxStage;
+__host__ __device__ inline size_t build_lds_bytes(int ccap, int stage = kMaxStage) {
+  return sizeof(int32_t) * (27 * 3 + 28 + 2 * (size_t)stage + 2 * (size_t)ccap) +
+         sizeof(double) * 3 * (size_t)ccap + (size_t)stage;
 }
 
-__device__ __forceinline__ BuildLds carve_build_lds(char* p, int ccap) {
+__device__ __forceinline__ BuildLds carve_build_lds(char* p, int ccap, int stage = kMaxStage) {
   BuildLds L;
   // doubles first (8-byte aligned at the start of dynamic LDS)
   L.cx = reinterpret_cast<double*>(p);
@@ -260,8 +264,8 @@ __device__ __forceinline__ BuildLds carve_build_lds(char* p, int ccap) {
   L.code = w + 54;
   L.off = w + 81;
   L.raw = w + 109;
-  L.idx = L.raw + kMaxStage;
-  L.center = L.idx + kMaxStage;
+  L.idx = L.raw + stage;
+  L.center = L.idx + stage;
   L.base = L.center + ccap;
   L.cell = reinterpret_cast<int8_t*>(L.base + ccap);
   return L;
@@ -335,15 +339,13 @@ __device__ __forceinline__ void rank_stage(const BuildLds& L, int lane, int T, i
 // The distance tests of every centre atom against the staged candidates
 // (positions px.., image shifts sx.., entries ent.. in registers, T of them),
 // appending the admitted ones to the centre atoms' rows in candidate order.
+template <int kC>
 __device__ __forceinline__ void test_stage(const Geometry& g, const State& s, const RepDev& rp,
                                            const BuildLds& L, int lane, int T, int n_c,
-                                           const double (&px)[kBuildChunks],
-                                           const double (&py)[kBuildChunks],
-                                           const double (&pz)[kBuildChunks],
-                                           const double (&sx)[kBuildChunks],
-                                           const double (&sy)[kBuildChunks],
-                                           const double (&sz)[kBuildChunks],
-                                           const uint32_t (&ent)[kBuildChunks]) {
+                                           const double (&px)[kC], const double (&py)[kC],
+                                           const double (&pz)[kC], const double (&sx)[kC],
+                                           const double (&sy)[kC], const double (&sz)[kC],
+                                           const uint32_t (&ent)[kC]) {
   const double Lx = rp.box[0], Ly = rp.box[1], Lz = rp.box[2];
   const double rl2 = g.rl2;
   const int64_t N = g.n;
@@ -354,7 +356,7 @@ __device__ __forceinline__ void test_stage(const Geometry& g, const State& s, co
     const double qx = L.cx[u], qy = L.cy[u], qz = L.cz[u];
     int base = L.base[u];
 #pragma unroll
-    for (int k = 0; k < kBuildChunks; ++k) {
+    for (int k = 0; k < kC; ++k) {
       if (k * 64 >= T) break;
       const double dx = fma(sx[k], Lx, px[k] - qx);
       const double dy = fma(sy[k], Ly, py[k] - qy);
@@ -402,16 +404,14 @@ __device__ __forceinline__ void finish_cell(const Geometry& g, const State& s, c
 
 // Candidate registers of stage slots p = k * 64 + lane (< T): position, image
 // shift and list entry; empty slots sit infinitely far away (r^2 = inf fails).
+template <int kC>
 __device__ __forceinline__ void load_candidates(const State& s, const BuildLds& L, int lane, int T,
-                                                double (&px)[kBuildChunks],
-                                                double (&py)[kBuildChunks],
-                                                double (&pz)[kBuildChunks],
-                                                double (&sx)[kBuildChunks],
-                                                double (&sy)[kBuildChunks],
-                                                double (&sz)[kBuildChunks],
-                                                uint32_t (&ent)[kBuildChunks]) {
+                                                double (&px)[kC], double (&py)[kC],
+                                                double (&pz)[kC], double (&sx)[kC],
+                                                double (&sy)[kC], double (&sz)[kC],
+                                                uint32_t (&ent)[kC]) {
 #pragma unroll
-  for (int k = 0; k < kBuildChunks; ++k) {
+  for (int k = 0; k < kC; ++k) {
     const int p = k * 64 + lane;
     px[k] = py[k] = pz[k] = HUGE_VAL;
     sx[k] = sy[k] = sz[k] = 0.0;
@@ -435,8 +435,8 @@ __device__ __forceinline__ void load_candidates(const State& s, const BuildLds& 
 // candidate (Sec. III-C: the candidate filter), admitted when r^2 < (r_c +
 // skin)^2 under the stencil cell's image shift; rows in stencil-cell order,
 // by id within a cell.  The stencil's candidates are staged in batches of at
-// most kMaxStage.
-template <bool kWave>
+// most kStage (the batches do not change the rows).
+template <bool kWave, int kStage = kMaxStage>
 __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, const CellTile& ct,
                                            const BuildLds& L, int lane) {
   const RepDev& rp = g.reps[ct.rep];
@@ -474,7 +474,7 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
     // the largest run of stencil cells whose candidates fit the stage (one
     // cell always fits: the capacity is at most kMaxStage)
     int s1 = s0 + 1;
-    while (s1 < 27 && L.off[s1 + 1] - L.off[s0] <= kMaxStage) ++s1;
+    while (s1 < 27 && L.off[s1 + 1] - L.off[s0] <= kStage) ++s1;
     const int base_off = L.off[s0];
     const int T = L.off[s1] - base_off;
     // each stencil cell's lane marks its slots, then every lane loads its slots
@@ -490,11 +490,12 @@ __device__ __forceinline__ void build_cell(const Geometry& g, const State& s, co
     build_sync<kWave>();
     rank_stage<kWave>(L, lane, T, base_off);
     // candidates into registers (L.cell is per stencil cell, unchanged by the sort)
-    double px[kBuildChunks], py[kBuildChunks], pz[kBuildChunks];
-    double sx[kBuildChunks], sy[kBuildChunks], sz[kBuildChunks];
-    uint32_t ent[kBuildChunks];
-    load_candidates(s, L, lane, T, px, py, pz, sx, sy, sz, ent);
-    test_stage(g, s, rp, L, lane, T, n_c, px, py, pz, sx, sy, sz, ent);
+    constexpr int kC = kStage / 64;
+    double px[kC], py[kC], pz[kC];
+    double sx[kC], sy[kC], sz[kC];
+    uint32_t ent[kC];
+    load_candidates<kC>(s, L, lane, T, px, py, pz, sx, sy, sz, ent);
+    test_stage<kC>(g, s, rp, L, lane, T, n_c, px, py, pz, sx, sy, sz, ent);
     build_sync<kWave>();
     s0 = s1;
   }
@@ -1712,9 +1713,9 @@ __global__ __launch_bounds__(kPersistThreads) void k_bin_build_density(
   if (due) {
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int nwaves = (int)blockDim.x >> 6;
-    const size_t bl = (build_lds_bytes(g.cell_cap) + 15) & ~size_t(15);
+    const size_t bl = (build_lds_bytes(g.cell_cap, kSmallStage) + 15) & ~size_t(15);
     char* base = reinterpret_cast<char*>(lds_d4) + density_table_bytes(t.nr, PREC);
-    const BuildLds L = carve_build_lds(base + (size_t)wave * bl, g.cell_cap);
+    const BuildLds L = carve_build_lds(base + (size_t)wave * bl, g.cell_cap, kSmallStage);
     if (cond && !err && blockIdx.x == 0 && threadIdx.x == 0)
       *counter64(s.status, SW_REBUILDS) += 1ull;
     const int64_t gstride = (int64_t)gridDim.x * nwaves;
@@ -1725,7 +1726,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_bin_build_density(
     for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
       const CellTile ct = g.ctiles[b];
       if (ct.cell < 0 || (rcond && rcond[ct.rep] == 0)) continue;
-      build_cell<true>(g, s, ct, L, lane);
+      build_cell<true, kSmallStage>(g, s, ct, L, lane);
       build_sync<true>();  // the wave's next cell reuses its staging arrays
     }
     if (!grid_sync(s.status)) return;
@@ -1752,7 +1753,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_bin_build_density(
 
 size_t bbd_lds_bytes(const Tables& t, int prec, int cell_cap) {
   return density_table_bytes(t.nr, prec) +
-         (size_t)(kPersistThreads / 64) * ((build_lds_bytes(cell_cap) + 15) & ~size_t(15));
+         (size_t)(kPersistThreads / 64) * ((build_lds_bytes(cell_cap, kSmallStage) + 15) & ~size_t(15));
 }
 
 template <int PREC, int LPA>
