@@ -56,7 +56,8 @@ typedef int32_t md_status;
 #define MD_E_ORDER (-8)         /* call out of order (e.g. md_step before md_build_neighbors) */
 #define MD_E_LOST_ATOM (-9)     /* an atom moved more than one box length past a periodic edge */
 #define MD_E_WORKSPACE (-10)    /* workspace too small or misaligned */
-#define MD_E_STALL (-11)        /* a grid barrier of a persistent launch timed out */
+#define MD_E_STALL (-11)        /* a grid barrier of a persistent launch timed out, or a
+                                   one-XCD launch found too few workgroups on that XCD */
 #define MD_W_RHO_RANGE 1        /* some rho_i exceeded the F table's last knot; F continued
                                    along its end tangent there */
 
@@ -84,13 +85,19 @@ typedef int32_t md_status;
 
 /* How md_step launches a chunk of chunk_steps steps.
  * MD_LAUNCH_GRAPH: a captured hipGraph of four kernels per step (binning and
- *   list build run only when flagged).
+ *   list build run only when flagged).  Small systems (the whole rebuild fits
+ *   at most 64 co-resident workgroups; one atom type, full list, one lanes-
+ *   per-atom value) fold binning, list build and density pass into one kernel
+ *   with grid barriers, so a step without a rebuild is two kernels.
  * MD_LAUNCH_PERSISTENT: one cooperative launch runs the whole chunk, its
  *   workgroups meeting at grid barriers between the phases of each step (for
  *   small systems, where the graph's per-kernel launch cost dominates the
  *   step; the paper's case for time steps per second at small N, Sec. II-B).
- *   Full list and one atom type only; results are bitwise those of the graph.
- *   A barrier that waits too long ends the launch with MD_E_STALL. */
+ *   A system whose atom tiles fit one thread each on the workgroups of one
+ *   XCD runs there with its per-atom state in registers; larger ones use
+ *   every XCD.  Full list and one atom type only; results are bitwise those
+ *   of the graph.  A barrier that waits too long ends the launch with
+ *   MD_E_STALL. */
 #define MD_LAUNCH_GRAPH 0
 #define MD_LAUNCH_PERSISTENT 1
 
