@@ -294,7 +294,7 @@ hipError_t launch_halfkick(const Launch& L, const Geometry& g, const State& s, d
 // the state with position buffer 0 / 1 current (buffer 0 current at entry).
 hipError_t launch_persist(const Launch& L, const Geometry& g, const State& s0, const State& s1,
                           const Tables& t, int precision, int lpa, int32_t nsteps, int64_t ncells,
-                          int grid, int one_xcd);
+                          int grid, int small);
 hipError_t allow_persist_lds(const Tables& t, int precision, int cell_cap);
 size_t persist_lds_bytes(const Tables& t, int precision, int cell_cap);
 hipError_t launch_energy(const Launch& L, const Geometry& g, const State& s, const Tables& t,

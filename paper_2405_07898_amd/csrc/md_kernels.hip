@@ -1336,7 +1336,6 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
   // the first barrier also publishes one decision on errors latched before the launch
   if (!grid_sync(status)) return;
   const int32_t pid = (int32_t)blockIdx.x, np = (int32_t)gridDim.x;
-  auto sync = [&](bool) { return grid_sync(status); };
   const int64_t gstride = (int64_t)np * nwaves;
   const int64_t gwave = (int64_t)pid * nwaves + wave;
   const int tpi = (int)blockDim.x / (64 * LPA);
@@ -1353,14 +1352,14 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
     if (rebuild) {
       if (pid == 0 && threadIdx.x == 0) *counter64(status, SW_REBUILDS) += 1ull;
       for (int64_t b = gwave; b < g.n_atiles; b += gstride) bin_tile(g, s, g.atiles[b], rf_cur, lane);
-      if (!sync(true)) return;
+      if (!grid_sync(status)) return;
       for (int64_t b = gwave; b < g.n_ctiles; b += gstride) {
         const CellTile ct = g.ctiles[b];
         if (ct.cell < 0 || rf_cur[ct.rep] == 0) continue;
         build_cell<true>(g, s, ct, L, lane);
         build_sync<true>();  // the wave's next cell reuses its staging arrays
       }
-      if (!sync(false)) return;
+      if (!grid_sync(status)) return;
     }
     // density pass; side jobs: zero the bins after a rebuild, clear the next
     // step's rebuild flags
@@ -1388,7 +1387,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
         store_fprime<PREC>(s, t, s.pos, i, rho_i, 0);
       }
     }
-    if (!sync(false)) return;
+    if (!grid_sync(status)) return;
     // force pass fused with the leap-frog update, into the other buffer
     if (pid == 0 && threadIdx.x == 0) *counter64(status, SW_STEPS) += 1ull;
     {
@@ -1416,7 +1415,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(Geometry g, State s
         }
       }
     }
-    if (!sync(false)) return;
+    if (!grid_sync(status)) return;
   }
 }
 
