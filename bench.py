@@ -283,16 +283,17 @@ def bench_headline(torch, md, configs, tabs, args, copy_gbs):
 
 # ------------------------------------------------------------------ secondaries
 
-def bench_c1(torch, md, configs, tabs, persistent=True):
+def bench_c1(torch, md, configs, tabs, persistent=True, lpa=0):
     """2,000-atom box (launch-latency regime): 100 steps as one captured graph
     from the prepared state (the workload's own length), a longer 2,000-step
     window, and one persistent cooperative launch per chunk for comparison
     (skipped with persistent=False: rocprofv3 ends with a segmentation fault
     after cooperative launches, before it writes its results)."""
     box = configs.config_small()
-    s = make_system(md, box, tabs, precision=md.MD_FP64)
-    lpa, _ = s.autotune(50)
-    s.close()
+    if lpa <= 0:
+        s = make_system(md, box, tabs, precision=md.MD_FP64)
+        lpa, _ = s.autotune(50)
+        s.close()
     s = make_system(md, box, tabs, precision=md.MD_FP64, lpa=lpa)
     pe0, ke0 = s.energy()
     sec100, _ = time_steps(torch, s, 100)  # one 100-step graph from the prepared state
@@ -866,6 +867,9 @@ def main() -> int:
     ap.add_argument("--lpa", type=int, default=0)
     ap.add_argument("--c1-graph-only", action="store_true",
                     help="c1 without its persistent-launch comparison (for rocprofv3 runs)")
+    ap.add_argument("--c1-lpa", type=int, default=0,
+                    help="c1's lanes per atom (0: the autotuner's pick, whose timings under "
+                         "rocprofv3 differ from a plain run)")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--sequential-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=512,
@@ -903,7 +907,8 @@ def main() -> int:
     sections = set() if args.no_secondary else set(args.sections.split(","))
     big, snaps, fm_problem = None, [], None
     if "c1" in sections:
-        out["c1_2000"] = bench_c1(torch, md, configs, tabs, persistent=not args.c1_graph_only)
+        out["c1_2000"] = bench_c1(torch, md, configs, tabs, persistent=not args.c1_graph_only,
+                                  lpa=args.c1_lpa)
         log(f"  c1: {out['c1_2000']}")
     if "c2" in sections:
         out["c2_10000"] = bench_c2_series(torch, md, configs, tabs)

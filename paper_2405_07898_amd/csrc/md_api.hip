@@ -1400,9 +1400,18 @@ namespace {
 // The rebuild flags written go to scratch words; the caller restores the state.
 md_status time_rounds(md_ctx* c, int lpa, int reps, hipEvent_t e0, hipEvent_t e1, float* us) {
   State& s = c->st[c->cur];
+  // the kernels a step launches: a small system's density pass runs inside
+  // its fused binning + build + density node (here with a flag that is never
+  // set, as in the steps without a rebuild)
+  const bool fused = c->binbuild_grid && lpa > 0 && !c->multi && !c->half;
   for (int r = 0; r <= reps; ++r) {
     if (r == 1) HIPC(c, hipEventRecord(e0, c->L.stream));
-    HIPC(c, density_pass(c, s, lpa, s.pos, nullptr, nullptr, nullptr, false));
+    if (fused)
+      HIPC(c, launch_bin_build_density(c->L, c->g, s, c->t, c->p.precision, lpa,
+                                       c->status + SW_ZERO, nullptr, nullptr, nullptr, c->sz.cells,
+                                       c->binbuild_grid));
+    else
+      HIPC(c, density_pass(c, s, lpa, s.pos, nullptr, nullptr, nullptr, false));
     HIPC(c, force_integrate_pass(c, s, lpa, s.pos, c->st[1 - c->cur].pos, c->status + SW_SCRATCH,
                                  s.rflag + 2 * c->n_rep));
   }

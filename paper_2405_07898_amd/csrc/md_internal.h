@@ -43,6 +43,7 @@ enum StatusWord : int {
   SW_MAX_CELL = 4,
   SW_SCRATCH = 5,      // throw-away flag for timing launches
   SW_TYPE_CHECK = 6,   // set when md_set_types finds a type out of range
+  SW_ZERO = 7,         // no kernel writes it: the never-due rebuild flag of timing launches
   SW_STEPS = 8,        // int64
   SW_REBUILDS = 10,    // int64
   SW_LIST_TOTAL = 12,  // int64
