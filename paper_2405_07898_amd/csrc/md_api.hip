@@ -441,6 +441,7 @@ md_status forces_now(md_ctx* c, bool want_rho) {
 // 8 / lanes_per_atom tiles of 64 atoms at once), at most one XCD's share of
 // the resident workgroups.
 int64_t persist_small_blocks(const md_ctx* c) {
+  if (c->lpa <= 0) return 0;  // per-replica schedules never run persistent
   const int per = std::max(1, (kPersistThreads / 64) / c->lpa);
   const int64_t need = (c->g.n_atiles + per - 1) / per;
   const int64_t fit = std::min<int64_t>(std::max(c->persist_cap, kXcd) / kXcd, kMaxSlots);
