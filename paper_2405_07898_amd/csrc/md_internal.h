@@ -9,7 +9,6 @@ namespace mdk {
 
 // ---------------------------------------------------------------- constants
 
-constexpr int kBlock = 256;          // threads per block of the per-atom passes
 constexpr int kBuildBlock = 64;      // one wave per cell in the list build
 constexpr int kMaxStage = 256;       // candidates staged per build batch (>= kMaxCellCap)
 constexpr int kMaxCellCap = 256;     // hard limit of cell_capacity
@@ -28,7 +27,6 @@ constexpr int32_t ST_NBR_OVERFLOW = 1;
 constexpr int32_t ST_CELL_OVERFLOW = 2;
 constexpr int32_t ST_NONFINITE = 4;
 constexpr int32_t ST_LOST = 8;
-constexpr int32_t ST_BAD_TYPE = 16;
 constexpr int32_t ST_STALL = 32;      // a grid barrier of the persistent launch timed out
 constexpr int32_t ST_PLACEMENT = 64;  // a one-XCD persistent launch found too few workgroups on XCD 0
 constexpr int32_t ST_ERR_MASK = 0xff;

@@ -9,8 +9,8 @@
 // Newton-Raphson).
 //
 // Compiled with -ffp-contract=off: every fused multiply-add below is written
-// as fma(); the list build and binning reproduce the reference expression
-// order exactly (bit-identical cells and neighbour sets).
+// as fma(); the list build and binning evaluate each expression in the plain
+// order of its definition (bit-identical cells and neighbour sets).
 #include "md_device.h"
 
 #include <math.h>
@@ -220,11 +220,10 @@ __global__ __launch_bounds__(64) void k_bin(Geometry g, State s, const int32_t* 
 //
 // The shift of a candidate is that of its stencil cell (a wrapped cell index
 // means one box length).  For every pair within the list radius this is the
-// minimum image, and d = fma(s, L, x_j - x_i) rounds exactly like the
-// reference's x_j - x_i followed by -L / +L, so the admitted set is
-// bit-identical to the reference's; pairs at other images are farther than the
+// minimum image, and d = fma(s, L, x_j - x_i) rounds exactly like x_j - x_i
+// followed by adding -L or +L, so the admitted set is bit-identical to that of
+// the plain minimum-image rule; pairs at other images are farther than the
 // list radius under either rule.
-constexpr int kBuildChunks = kMaxStage / 64;
 // Candidates staged per batch in the small-system node, whose 512-thread
 // workgroups have registers to spare: at about 9 atoms per cell a stencil
 // often holds more than kMaxStage, and a second batch doubles the cell's chain.
@@ -1233,26 +1232,21 @@ __host__ __device__ inline size_t persist_table_bytes(int nr, int prec) {
   return (b + 15) & ~size_t(15);
 }
 
-// Barrier of the np workgroups of a persistent launch (an arrival counter, a
+// Barrier of all workgroups of a persistent launch (an arrival counter, a
 // generation word and the last arrival's stop decision, all accessed only by
 // atomics; the wait is bounded).  Each thread's stores have completed before
 // its workgroup arrives, and the spin polls with relaxed loads: one fence on
-// each side per workgroup, not one per poll.
-//   kOneL2 = false: the workgroups may sit on different XCDs, whose L2 caches
-//     are not coherent with each other, so the arrival writes this XCD's L2
-//     back and the departure invalidates it (agent-scope release / acquire).
-//   kOneL2 = true: every workgroup runs on the same XCD and so shares one L2:
-//     stores complete into that L2 before the arrival and nothing is written
-//     back, so the lines the phases write stay dirty in the L2, which the
-//     departure's invalidation keeps.  Data that the phases exchange through
-//     atomics (the bin counts) cross full barriers.
-template <bool kOneL2>
-__device__ bool part_sync(int32_t* status, int32_t np) {
+// each side per workgroup, not one per poll.  The workgroups may sit on
+// different XCDs, whose L2 caches are not coherent with each other, so the
+// arrival writes this XCD's L2 back and the departure invalidates it
+// (agent-scope release / acquire).
+__device__ bool grid_sync(int32_t* status) {
+  const int32_t np = (int32_t)gridDim.x;
   __shared__ int32_t s_go;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (!kOneL2) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     int32_t* count = status + SW_BAR_COUNT;
     int32_t* gen = status + SW_BAR_GEN;
     int32_t* stop = status + SW_BAR_STOP;
@@ -1283,18 +1277,13 @@ __device__ bool part_sync(int32_t* status, int32_t np) {
     }
     // invalidates this CU's L1 and the clean lines of the L2 (an invalidation
     // at workgroup scope leaves the L1 alone in a dispatch whose workgroups
-    // are not split over CUs; dirty L2 lines stay, so with one L2 the data of
-    // the phase just ended is still there)
+    // are not split over CUs)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);  // the invalidation is done before any wave reads on
     s_go = go > 0;
   }
   __syncthreads();
   return s_go != 0;
-}
-
-__device__ __forceinline__ bool grid_sync(int32_t* status) {
-  return part_sync<false>(status, (int32_t)gridDim.x);
 }
 
 // The XCD this wave runs on (hardware register XCC_ID, bits 3:0).
