@@ -260,9 +260,12 @@ md_status md_build_neighbors(md_ctx* ctx);
  * chunk_steps) run as one shorter captured graph, kept for reuse (a few
  * lengths at a time).  With MD_LAUNCH_PERSISTENT the left-over steps are
  * launched kernel by kernel.  On an error the state rolls back to the start
- * of the graph (or chunk) in which it occurred (the status is returned;
- * md_stats().steps tells where).  n = 0 takes no step and returns the latched
- * status; n < 0 is MD_E_ARG. */
+ * of the graph (or chunk) in which it occurred and the list is rebuilt there
+ * (the status is returned; md_stats().steps tells where).  Should that
+ * rebuild fail as well, no list is valid: md_step, md_compute_forces and
+ * md_get_state with forces return MD_E_ORDER until md_set_state and
+ * md_build_neighbors start over.
+ * n = 0 takes no step and returns the latched status; n < 0 is MD_E_ARG. */
 md_status md_step(md_ctx* ctx, int64_t n);
 
 /* Capture, without running them, the graphs that md_step(n) would launch

@@ -1169,7 +1169,11 @@ md_status md_step(md_ctx* c, int64_t n) {
     HIPC(c, launch_snapshot(c->L, c->g, c->st[0], c->snap_pos, c->snap_vel, true));
     md_status r = rebuild_sorted(c, true);
     if (r == MD_OK) r = forces_now(c, false);
-    HIPC(c, hipStreamSynchronize(c->L.stream));
+    if (r == MD_OK) r = read_status(c, w);
+    // the list built at the restored positions can overflow in turn (it was
+    // last built at other positions): then no list is valid and md_step
+    // refuses to run until md_set_state starts over
+    if (r != MD_OK || status_code(w[SW_BITS]) < 0) c->built = false;
     return s;
   }
   return s;
