@@ -219,3 +219,36 @@ def test_prepare_captures_without_stepping(md, tabs):
     xb, vb, fb, sb = run(False)
     assert sa["steps"] == sb["steps"] == 48
     assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("launch", [0, 1], ids=["graph", "persistent"])
+def test_contexts_with_different_table_sizes_coexist(md, tabs, launch):
+    """Contexts set the pair kernels' dynamic-LDS limits for their own tables.
+    A context created later with smaller tables (200 knots instead of 2,000)
+    must not take the room from an earlier one: the first context's steps
+    after the second is created are bitwise those of a run without it."""
+    box = configs.small_box(6, seed=91, temperature=1500.0, sigma_x=0.05)
+    small = P.md_tables(n_knots=200)
+    _say(f"[gpu] contexts with 2,000- and 200-knot tables, n={box.n}, launch={launch}")
+
+    def make(t):
+        s = md.System(_params(md, chunk_steps=10, launch_mode=launch), t, [box.n],
+                      box.box[None, :])
+        s.set_state(box.x, box.v)
+        s.build_neighbors()
+        return s
+
+    a = make(tabs)
+    a.step(40)
+    ref = [t.cpu().numpy() for t in a.get_state()]
+    a.close()
+    a = make(tabs)
+    a.step(20)
+    b = make(small)
+    b.step(20)
+    a.step(20)
+    got = [t.cpu().numpy() for t in a.get_state()]
+    a.close()
+    b.close()
+    for r, g in zip(ref, got):
+        assert np.array_equal(r, g)
